@@ -1,0 +1,266 @@
+/*
+ * librqc -- sliced tensor-network amplitudes and rejection sampling for random
+ * quantum circuits on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow arXiv 2112.15083 ("Classical sampling of random
+ * quantum circuits with bounded fidelity"):
+ *   - a circuit's amplitudes <x|C|0> for batches of bitstrings sharing fixed
+ *     bits (introduction: batches of amplitudes; Sec. II.A: b = (b_A, b_B));
+ *   - contraction along a tree T with sliced ("projected") variables I summed at
+ *     the very last step (Sec. I, first paragraphs), optionally partially: the
+ *     slices X x {0,1}^{|I|-|S|} of Sec. I.C, normalised by 1/sqrt(F);
+ *   - the modified frugal rejection sampling of Sec. II.A.
+ *
+ * Memory and threading
+ *   Handles are opaque and owned by the caller (create/destroy pairs).  All
+ *   data buffers are owned by the caller.  "device" pointers are HIP device
+ *   addresses on the current device; "host" pointers are ordinary memory.  The
+ *   library allocates only its plan workspace (leaf tensors, intermediate arena,
+ *   FP64 accumulators), through the allocator in rqc_plan_opts or hipMalloc.
+ *   Calls that take a stream enqueue their GPU work on it and return; unless a
+ *   call says otherwise, results are ready when that stream is synchronised.
+ *   A plan may be used by one thread at a time; distinct plans are independent.
+ *
+ * Errors
+ *   Every call returns an rqc_status.  On a non-OK status nothing was written to
+ *   the outputs unless stated, and rqc_last_error() returns a thread-local
+ *   message describing the failure.  No C++ exception crosses this interface.
+ *
+ * Conventions
+ *   Qubit q is bit q of every bitstring integer.  A batch of 2^o amplitudes is
+ *   indexed by t in [0, 2^o): bit b of t is the value of qubit open_qubits[b];
+ *   the other qubits take their bits from the batch's fixed-bit mask.
+ *   Complex64 values are interleaved (re, im) float pairs; complex128 likewise
+ *   with doubles.
+ *   Variables (tensor legs; Appendix B calls them vertices): ids 0..n-1 are the
+ *   qubit inputs (fixed to |0>); walking the gate lines in order, each
+ *   single-qubit gate creates one variable (its output), an fSim with
+ *   theta = pi/2 creates none (it equals SWAP times a diagonal gate), any other
+ *   two-qubit gate creates two (first qubit first).
+ *
+ * Circuit text: see rqc_load_circuit.
+ */
+#ifndef RQC_H
+#define RQC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rqc_circuit rqc_circuit;
+typedef struct rqc_plan rqc_plan;
+
+typedef enum {
+    RQC_OK = 0,
+    RQC_EINVAL = -1,  /* bad argument */
+    RQC_EPARSE = -2,  /* malformed circuit text */
+    RQC_EPLAN = -3,   /* no plan satisfies the options */
+    RQC_ENOMEM = -4,  /* workspace allocation failed or exceeds the budget */
+    RQC_EDEVICE = -5, /* HIP runtime error, or no GPU / wrong architecture */
+    RQC_ESHORT = -6   /* sampler: fewer accepted samples than requested */
+} rqc_status;
+
+typedef enum {
+    RQC_C64 = 0,    /* complex64 contraction, FP32 MFMA, FP32 accumulate */
+    RQC_BF16X3 = 1, /* GEMMs as 3 bfloat16 split products, FP32 accumulate */
+    RQC_FP16X3 = 2  /* GEMMs as 3 float16 split products with 2^e scaling */
+} rqc_precision;
+
+/* Device allocator used for the plan workspace.  Must return memory usable by
+   kernels on the current device, aligned to 256 bytes, or NULL on failure. */
+typedef void *(*rqc_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*rqc_free_fn)(void *ptr, void *ctx);
+
+typedef struct {
+    /* Slicer memory target: slice until every intermediate tensor has at most
+       2^max_log2_tensor elements (0 = no memory target). */
+    int32_t max_log2_tensor;
+    /* Slicer leg-count target: slice at least this many legs, each chosen to
+       minimise the total sliced cost (-1 = memory target only). */
+    int32_t n_sliced_target;
+    /* Slices whose legs are carried as an extra tensor mode ("batched") instead
+       of being looped over: the largest batched tensor has at most
+       2^max_log2_batched elements (0 = 28). */
+    int32_t max_log2_batched;
+    /* rqc_precision of the contraction GEMMs. */
+    int32_t precision;
+    /* Partial slicing (Sec. I.B, Appendix B Alg. 1).  target_fidelity >= 1 or
+       <= 0: full slicing.  Otherwise k0 = ceil(3 - log2 f) partially sliced
+       vertices are chosen by SlicedVertexSelect among the sliced legs, their
+       norms R are computed on the GPU and X is the minimal top-R set reaching f.
+       partial_k > 0 overrides k0; partial_count > 0 keeps exactly that many
+       top-R indices instead of the sum rule. */
+    double target_fidelity;
+    int32_t partial_k;
+    int32_t partial_count;
+    /* Greedy path search: number of randomised trials (0 = 16) and RNG seed. */
+    int32_t path_trials;
+    uint64_t path_seed;
+    /* 1 = time every kernel class with HIP events (see rqc_plan_profile). */
+    int32_t profile;
+    /* 1 = plan on the host only: no device is touched and the plan can only be
+       inspected (rqc_plan_info and friends), not executed. */
+    int32_t dry_run;
+    /* Workspace allocator (NULL alloc = hipMalloc / hipFree). */
+    rqc_alloc_fn alloc;
+    rqc_free_fn free;
+    void *alloc_ctx;
+} rqc_plan_opts;
+
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_open;
+    int32_t n_variables;
+    int32_t n_sliced;          /* |I| */
+    int32_t n_batched;         /* sliced legs carried as a tensor mode */
+    int32_t n_partial;         /* k = |S| (0 for full slicing) */
+    int64_t n_slices;          /* slices in the plan's default slice list */
+    int64_t n_partial_kept;    /* |X| */
+    double fidelity;           /* F = sum_{i in X} R[i]; 1 for full slicing */
+    double flops_per_batch;    /* algorithmic flops (8 per complex multiply-add)
+                                  of one open batch over the default slice list */
+    double flops_unsliced;     /* the same for the tree without slicing */
+    double gemm_flop_share;    /* share of flops_per_batch in MFMA GEMM steps */
+    double bytes_per_batch;    /* algorithmic HBM bytes: each step's operands read
+                                  once and result written once, plus permutes */
+    int32_t max_log2_tensor;   /* largest intermediate (with batched slice legs) */
+    int32_t n_steps;           /* pairwise contractions in the tree */
+    int32_t n_launches;        /* kernel launches per slice group */
+    int64_t n_groups;          /* slice groups per batch */
+    int64_t workspace_bytes;   /* device memory held by the plan */
+    double plan_seconds;       /* host time spent planning */
+} rqc_plan_info_t;
+
+typedef struct {
+    int64_t accepted;   /* accepted batches (may exceed the samples returned) */
+    int64_t batches;    /* batches examined */
+    int64_t batches_used; /* batches up to the one that gave the last sample kept */
+    double eps_J;       /* sum over examined batches of max(0, p_j - alpha/N_B) */
+    double p_total;     /* sum of all examined p_j (normalised units) */
+} rqc_sample_stats;
+
+/* Kernel classes reported by rqc_plan_profile. */
+enum {
+    RQC_K_LEAF = 0,      /* slice/fixed-bit selection of leaf tensors */
+    RQC_K_SMALL = 1,     /* fused small-subtree contraction in LDS */
+    RQC_K_STREAM = 2,    /* streaming small-K contraction (HBM bound) */
+    RQC_K_PERMUTE = 3,   /* tensor permute */
+    RQC_K_GEMM = 4,      /* complex GEMM on MFMA */
+    RQC_K_ACCUM = 5,     /* FP64 cross-slice accumulation */
+    RQC_K_FINAL = 6,     /* normalisation and output conversion */
+    RQC_K_SAMPLE = 7,    /* probabilities and rejection sampling */
+    RQC_K_CLASSES = 8
+};
+
+typedef struct {
+    int64_t launches[RQC_K_CLASSES];
+    double seconds[RQC_K_CLASSES];   /* summed HIP-event durations */
+    double flops[RQC_K_CLASSES];     /* algorithmic flops of the timed launches */
+    double bytes[RQC_K_CLASSES];     /* algorithmic bytes of the timed launches */
+} rqc_profile_t;
+
+/*
+ * Parse circuit text.  Format ("rqc-circuit 1"; '#' starts a comment):
+ *   qubits <n>                    number of qubits, 1..64
+ *   grid <rows> <cols> / removed <r> <c> / cycles <m>   (informational)
+ *   sx|sy|sw <cycle> <q>          sqrt(P) = (I - iP)/sqrt(2), P in X, Y,
+ *                                 W = (X+Y)/sqrt(2)
+ *   fsim <cycle> <qa> <qb> <t> <p> fSim(pi*t, pi*p), t and p exact fractions;
+ *                                 matrix in the basis |b_qa b_qb>:
+ *                                 [[1,0,0,0],[0,c,-is,0],[0,-is,c,0],[0,0,0,e^{-i pi p}]]
+ * Gate lines are applied in order.  `text` is host memory of `len` bytes.
+ * Returns RQC_EPARSE (with the line number in rqc_last_error) on bad input.
+ */
+rqc_status rqc_load_circuit(const char *text, size_t len, rqc_circuit **out);
+rqc_status rqc_circuit_info(const rqc_circuit *c, int32_t *n_qubits, int32_t *n_variables,
+                            int32_t *n_gates);
+void rqc_circuit_destroy(rqc_circuit *c);
+
+/*
+ * Build a contraction plan (Sec. I: contraction tree T and sliced variables I).
+ *   path, n_path_pairs: optional contraction order as SSA pairs: leaf tensor t
+ *     is gate line t, and contraction number s creates tensor n_gates + s.
+ *     NULL = the library's randomised greedy path.
+ *   sliced_legs, n_sliced: optional variable ids to slice (NULL = greedy slicer
+ *     under opts).  Input variables and output variables cannot be sliced.
+ *   open_qubits[b]: the qubit carried by bit b of the batch index (host array).
+ * The plan uploads its leaf tensors and reserves its workspace on the current
+ * device.  opts may be NULL (defaults: no slicing, complex64).
+ */
+rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_path_pairs,
+                           const int32_t *sliced_legs, int32_t n_sliced,
+                           const int32_t *open_qubits, int32_t n_open,
+                           const rqc_plan_opts *opts, rqc_plan **out);
+rqc_status rqc_plan_info(const rqc_plan *p, rqc_plan_info_t *info);
+/* Sliced variable ids in slice-id bit order (bit t of a slice id = legs[t]). */
+rqc_status rqc_plan_sliced_legs(const rqc_plan *p, int32_t *legs, int32_t cap, int32_t *count);
+/* Partial slicing results: S (variable ids, bit t of an index i = S[t]), the
+   kept indices X in selection order, and R[0 .. 2^k) (host arrays; any may be
+   NULL; caps are element counts). */
+rqc_status rqc_plan_partial(const rqc_plan *p, int32_t *S, int32_t capS, uint64_t *X, int64_t capX,
+                            double *R, int64_t capR);
+rqc_status rqc_plan_profile(const rqc_plan *p, rqc_profile_t *out);
+rqc_status rqc_plan_profile_reset(rqc_plan *p);
+void rqc_plan_destroy(rqc_plan *p);
+
+/*
+ * Amplitudes of n_batches open batches (Sec. I.C partial contraction):
+ *   amp_b[t] = (1/sqrt(F)) * sum_{s in slices} <x_b(t)| C_s |0>
+ * where x_b(t) combines fixed_bits[b] (host array of n-bit masks; open bits
+ * ignored) with t on the open qubits, C_s is the network with the sliced
+ * variables fixed to the bits of slice id s, and the sum runs in FP64 in the
+ * plan's fixed slice order (independent of how slices are grouped).
+ *   slice_ids: host array of slice ids, or NULL for the plan's default list
+ *     (all 2^|I| slices, or X x {0,1}^{|I|-|S|} under partial slicing).  A
+ *     custom list must be a union of whole batched-slice groups.
+ *   out_amps: device complex64 [n_batches][2^n_open].
+ *   out_f64: optional device complex128 [n_batches][2^n_open] receiving the
+ *     same normalised amplitudes before rounding to complex64.
+ *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
+ * Asynchronous on hip_stream.
+ */
+rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64_t n_slices,
+                                   const uint64_t *fixed_bits, int64_t n_batches, void *out_amps,
+                                   void *out_f64, void *hip_stream);
+
+/*
+ * Modified frugal rejection sampling (Sec. II.A) over computed batches.
+ *   amps: device complex64 [n_batches][2^n_open]; each open batch is split into
+ *     sub-batches of N_A = 2^log2_NA amplitudes (bits 0..log2_NA-1 of the batch
+ *     index are b_A), so it holds 2^(n_open - log2_NA) sub-batches j, numbered
+ *     globally batch_index_base + b * 2^(n_open-log2_NA) + j_local.
+ *   fixed_bits: host masks of the batches (as in rqc_contract_amplitudes).
+ *   open_qubits: host array as in the plan.  N_B = 2^(n_qubits - log2_NA).
+ *   Per sub-batch, in global order: p_ij = re^2 + im^2 in FP64, p_j the
+ *   sequential FP64 sum, accept iff U0 < p_j * N_B / (alpha * F_norm), then
+ *   i = first index whose sequential prefix sum exceeds U1 * p_j (else the last
+ *   i with p_ij > 0), U_d = Philox4x32-10 uniform (key = seed, counter =
+ *   (global sub-batch index, d, 0)).
+ *   pick_steps > 0 selects the literal "pick j at random" mode instead: the
+ *     amps hold one full vector (n_batches = 1, all qubits open); step t picks
+ *     j from Philox draw 2 at counter t and uses counter t for U0 and U1; up to
+ *     pick_steps steps are taken.
+ *   out_samples: device uint64 [n_samples] bitstrings, in ascending sub-batch
+ *     (or step) order; *n_out (host) receives the count; stats (host, optional).
+ * Synchronises hip_stream before returning.  Returns RQC_ESHORT if fewer than
+ * n_samples were accepted (the first *n_out entries are valid).
+ */
+rqc_status rqc_rejection_sample(const void *amps, const uint64_t *fixed_bits, int64_t n_batches,
+                                const int32_t *open_qubits, int32_t n_open, int32_t log2_NA,
+                                int32_t n_qubits, double alpha, double F_norm, uint64_t seed,
+                                uint64_t batch_index_base, int64_t pick_steps, int64_t n_samples,
+                                uint64_t *out_samples, int64_t *n_out, rqc_sample_stats *stats,
+                                void *hip_stream);
+
+/* Thread-local message for the last non-OK status (never NULL). */
+const char *rqc_last_error(void);
+/* Library version string. */
+const char *rqc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RQC_H */

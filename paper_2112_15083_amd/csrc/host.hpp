@@ -1,0 +1,163 @@
+// Internal host-side structures of librqc: circuit, hyper tensor network,
+// contraction tree, slicing and the lowered launch program.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rqc.h"
+
+namespace rqc {
+
+using cf = std::complex<float>;
+using cd = std::complex<double>;
+
+struct Error {
+    rqc_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(rqc_status code, const std::string &msg);
+
+// ------------------------------------------------------------------ circuit
+enum GateKind { G_SX = 0, G_SY = 1, G_SW = 2, G_FSIM = 3 };
+
+struct Gate {
+    int kind = 0;
+    int q[2] = {-1, -1};
+    long tnum = 0, tden = 1; // theta / pi
+    long pnum = 0, pden = 1; // phi / pi
+    bool swap_like() const { return kind == G_FSIM && 2 * tnum == tden; }
+};
+
+struct Circuit {
+    int n = 0;
+    std::vector<Gate> gates;
+};
+
+Circuit parse_circuit(const char *text, size_t len);
+
+// ------------------------------------------------------------------ network
+// One tensor per gate line.  Variables follow the numbering of rqc.h.
+struct Leaf {
+    std::vector<int> legs; // variable ids; legs[0] is bit 0 of the element index
+    std::vector<cf> data;  // 2^legs.size() values (input variables already fixed to 0)
+};
+
+struct Network {
+    int n_qubits = 0;
+    int n_vars = 0;
+    std::vector<Leaf> leaves;
+    std::vector<int> out_var;       // per qubit: variable on that wire at the end
+    std::vector<int> var_gate;      // creating gate line (-1 for inputs)
+    std::vector<std::vector<int>> gate_inputs; // input variables of each gate line
+};
+
+Network build_network(const Circuit &c);
+
+// ------------------------------------------------------------------ tree
+using Legs = std::vector<int>; // sorted variable ids
+
+struct Tree {
+    int n_leaves = 0;
+    std::vector<std::pair<int, int>> steps; // SSA operand ids; step s creates n_leaves + s
+    int root() const { return steps.empty() ? 0 : n_leaves + (int)steps.size() - 1; }
+};
+
+// Leg sets of every tensor of the tree (leaves then steps) for a given set of
+// removed (projected) variables and kept (never summed) variables.
+std::vector<Legs> tree_legs(const Tree &t, const std::vector<Legs> &leaf_legs, int n_vars,
+                            const std::vector<char> &removed, const std::vector<char> &kept);
+
+double tree_log2_cost_sum(const Tree &t, const std::vector<Legs> &legs); // log2 sum 2^|A u B|
+
+Tree greedy_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
+                 uint64_t seed, double temperature);
+
+std::vector<int> greedy_slice(const Tree &t, const std::vector<Legs> &legs, int n_vars,
+                              const std::vector<char> &forbidden, int max_log2_tensor,
+                              int n_target);
+
+// ------------------------------------------------------------------ light cones (Appendix B)
+struct LightCones {
+    // per variable: sorted list of vertices L'_C(v) (inputs of the gates v depends on)
+    std::vector<std::vector<int>> cone_vertices;
+};
+LightCones light_cones(const Network &net);
+std::vector<int> sliced_vertex_select(const LightCones &lc, const std::vector<int> &I, int k);
+
+// ------------------------------------------------------------------ lowered program
+enum OpKind { OP_SMALL = 0, OP_STREAM = 1, OP_PERMUTE = 2, OP_GEMM = 3 };
+
+// Bit map from a logical index to an element offset: sum over runs of
+// ((x >> src) & (2^len - 1)) << dst.
+constexpr int kMaxRuns = 24;
+struct BitMap {
+    uint8_t n = 0;
+    uint8_t src[kMaxRuns], len[kMaxRuns], dst[kMaxRuns];
+};
+BitMap make_map(const std::vector<int> &logical_to_mem); // entry = memory bit of logical bit, -1 = absent
+
+struct Buf {      // where a tensor lives
+    int kind = 0; // 0 = arena, 1 = projected-leaf buffer
+    int64_t off = 0; // element offset (complex64 elements)
+};
+
+struct SmallStep { // one contraction inside a fused small subtree
+    int a_kind, b_kind, c_kind; // 0 = LDS, 1 = leaf buffer, 2 = arena (root output)
+    int64_t a_off, b_off, c_off;
+    int rc, kc;                 // log2 |C|, log2 K
+    BitMap ax, bx, ay, by;      // C-index -> A/B offsets, K-index -> A/B offsets
+};
+
+struct SmallTree {
+    int first_step, n_steps;
+};
+
+struct StreamOp {   // C[x] = sum_y A[ax(x)+ay(y)] * B[bx(x)+by(y)]
+    Buf a, b, c;
+    int rc, kc;
+    BitMap ax, bx, ay, by;
+};
+
+struct PermuteOp {  // dst[pi(x)] = src[x]
+    Buf src, dst;
+    int r;
+    std::vector<int> perm; // perm[i] = destination bit of source bit i
+};
+
+struct GemmOp {     // C[b][m][n] = sum_k A[b][m][k] B[b][k][n] (complex)
+    Buf a, b, c;
+    int64_t batch, M, N, K;
+    int a_kfast;    // A element (m,k) at m*K + k if 1, k*M + m if 0
+    int b_nfast;    // B element (k,n) at k*N + n if 1, n*K + k if 0
+    int c_nfast;    // C element (m,n) at m*N + n if 1, n*M + m if 0
+    int64_t sa, sb, sc; // batch strides (elements)
+};
+
+struct Op {
+    int kind;
+    int index; // into the per-kind arrays
+    double flops, bytes;
+};
+
+struct Program {
+    std::vector<SmallStep> small_steps;
+    std::vector<SmallTree> small_trees;
+    int small_lds_elems = 0;
+    std::vector<StreamOp> streams;
+    std::vector<PermuteOp> permutes;
+    std::vector<GemmOp> gemms;
+    std::vector<Op> ops; // launch order (OP_SMALL appears once, first)
+    // final tensor
+    Buf root;
+    BitMap root_open, root_slice; // open-batch index / batched-slice index -> offset
+    int n_batched = 0;
+    int64_t arena_elems = 0;
+    int64_t leafbuf_elems = 0;
+    double flops = 0, bytes = 0, gemm_flops = 0;
+    int max_log2 = 0;
+};
+
+} // namespace rqc

@@ -1,0 +1,358 @@
+// HIP kernels of librqc for gfx950 (CDNA4, wave64).
+//
+//   k_leaf_select   slice / fixed-bit selection of the leaf tensors (Sec. I.C,
+//                   step 1: the sliced vertices take one value per slice)
+//   k_small_trees   one workgroup per small subtree, intermediates in LDS
+//   k_stream        streaming contraction with a short contracted dimension
+//   k_permute       LDS-tiled bit permutation of a tensor (coalesced both ways)
+//   k_cgemm_f32     complex GEMM on FP32 MFMA (v_mfma_f32_32x32x2f32)
+//   k_accumulate    FP64 cross-slice sum in a fixed slice order (Sec. I.C)
+//   k_finalize      1/sqrt(F) normalisation and complex64 output (Sec. I.C, step 2)
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace rqc {
+
+__device__ __forceinline__ int64_t map_apply(const BitMap &m, int64_t x) {
+    int64_t r = 0;
+    for (int i = 0; i < m.n; i++) r |= ((x >> m.src[i]) & ((1LL << m.len[i]) - 1)) << m.dst[i];
+    return r;
+}
+
+__device__ __forceinline__ void cmac(float2 &acc, float2 a, float2 b) {
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+}
+
+// ------------------------------------------------------------------ leaf select
+__global__ void __launch_bounds__(256) k_leaf_select(const float2 *__restrict__ full, float2 *__restrict__ leafbuf,
+                                                     const LeafSel *__restrict__ sel, int n_leaves, ProjVals vals) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int leaf = gid >> 4, e = gid & 15;
+    if (leaf >= n_leaves) return;
+    const LeafSel &d = sel[leaf];
+    if (e >= (1 << d.n_free)) return;
+    int64_t src = d.src;
+    for (int j = 0; j < d.n_free; j++)
+        if ((e >> j) & 1) src += (int64_t)1 << d.free_pos[j];
+    for (int j = 0; j < d.n_proj; j++) {
+        const int p = d.proj_idx[j];
+        if ((vals.w[p >> 6] >> (p & 63)) & 1) src += (int64_t)1 << d.proj_pos[j];
+    }
+    leafbuf[d.dst + e] = full[src];
+}
+
+void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_sel, int n_leaves, ProjVals vals,
+                        hipStream_t s) {
+    if (n_leaves <= 0) return;
+    const int threads = 256;
+    const int blocks = (n_leaves * 16 + threads - 1) / threads;
+    hipLaunchKernelGGL(k_leaf_select, dim3(blocks), dim3(threads), 0, s, full, leafbuf, d_sel, n_leaves, vals);
+}
+
+// ------------------------------------------------------------------ small subtrees
+__global__ void __launch_bounds__(256) k_small_trees(const SmallStep *__restrict__ steps,
+                                                     const SmallTree *__restrict__ trees,
+                                                     const float2 *__restrict__ leafbuf, float2 *__restrict__ arena) {
+    extern __shared__ float2 lds[];
+    const SmallTree t = trees[blockIdx.x];
+    for (int s = t.first_step; s < t.first_step + t.n_steps; s++) {
+        const SmallStep &st = steps[s];
+        const float2 *A = st.a_kind == 0 ? lds + st.a_off : (st.a_kind == 1 ? leafbuf + st.a_off : arena + st.a_off);
+        const float2 *B = st.b_kind == 0 ? lds + st.b_off : (st.b_kind == 1 ? leafbuf + st.b_off : arena + st.b_off);
+        float2 *C = st.c_kind == 0 ? lds + st.c_off : arena + st.c_off;
+        const int nC = 1 << st.rc, nK = 1 << st.kc;
+        for (int x = threadIdx.x; x < nC; x += blockDim.x) {
+            const int64_t ax = map_apply(st.ax, x), bx = map_apply(st.bx, x);
+            float2 acc = make_float2(0.f, 0.f);
+            for (int y = 0; y < nK; y++) cmac(acc, A[ax + map_apply(st.ay, y)], B[bx + map_apply(st.by, y)]);
+            C[x] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int n_trees, int lds_elems,
+                        const float2 *leafbuf, float2 *arena, hipStream_t s) {
+    if (n_trees <= 0) return;
+    hipLaunchKernelGGL(k_small_trees, dim3(n_trees), dim3(256), (size_t)lds_elems * sizeof(float2), s, d_steps,
+                       d_trees, leafbuf, arena);
+}
+
+// ------------------------------------------------------------------ streaming contraction
+struct StreamArgs {
+    const float2 *a;
+    const float2 *b;
+    float2 *c;
+    int64_t n;
+    int kc;
+    BitMap ax, bx, ay, by;
+};
+
+__global__ void __launch_bounds__(256) k_stream(StreamArgs p) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int nK = 1 << p.kc;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < p.n; x += stride) {
+        const int64_t ax = map_apply(p.ax, x), bx = map_apply(p.bx, x);
+        float2 acc = make_float2(0.f, 0.f);
+        for (int y = 0; y < nK; y++) cmac(acc, p.a[ax + map_apply(p.ay, y)], p.b[bx + map_apply(p.by, y)]);
+        p.c[x] = acc;
+    }
+}
+
+void launch_stream(const StreamOp &op, const float2 *a, const float2 *b, float2 *c, hipStream_t s) {
+    StreamArgs p;
+    p.a = a;
+    p.b = b;
+    p.c = c;
+    p.n = (int64_t)1 << op.rc;
+    p.kc = op.kc;
+    p.ax = op.ax;
+    p.bx = op.bx;
+    p.ay = op.ay;
+    p.by = op.by;
+    const int threads = 256;
+    int64_t blocks = (p.n + threads - 1) / threads;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(k_stream, dim3((unsigned)blocks), dim3(threads), 0, s, p);
+}
+
+// ------------------------------------------------------------------ permute
+PermDesc make_perm_desc(int r, const std::vector<int> &perm) {
+    PermDesc d;
+    const int t = r < 5 ? r : 5;
+    std::vector<char> inT(r, 0);
+    for (int i = 0; i < t; i++) inT[i] = 1;
+    for (int i = 0; i < r; i++)
+        if (perm[i] < t) inT[i] = 1;
+    std::vector<int> T, tb;
+    for (int i = 0; i < r; i++) (inT[i] ? T : tb).push_back(i);
+    d.tile_log = (int)T.size();
+    d.n_tiles = (int64_t)1 << tb.size();
+    std::vector<int> m1(tb.size()), m2(tb.size());
+    for (size_t j = 0; j < tb.size(); j++) m1[j] = tb[j], m2[j] = perm[tb[j]];
+    d.tile_src = make_map(m1);
+    d.tile_dst = make_map(m2);
+    std::vector<int> rd(T.size());
+    for (size_t j = 0; j < T.size(); j++) rd[j] = T[j];
+    d.rd = make_map(rd);
+    std::vector<int> W(T.size());
+    for (size_t j = 0; j < T.size(); j++) W[j] = (int)j; // positions in T
+    std::sort(W.begin(), W.end(), [&](int x, int y) { return perm[T[x]] < perm[T[y]]; });
+    std::vector<int> wl(T.size()), wd(T.size());
+    for (size_t j = 0; j < T.size(); j++) wl[j] = W[j], wd[j] = perm[T[W[j]]];
+    d.wr_lds = make_map(wl);
+    d.wr_dst = make_map(wd);
+    return d;
+}
+
+__global__ void __launch_bounds__(256) k_permute(PermDesc d, const float2 *__restrict__ src, float2 *__restrict__ dst) {
+    __shared__ float2 tile[1024 + 32];
+    const int n = 1 << d.tile_log;
+    for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
+        const int64_t bs = map_apply(d.tile_src, t), bd = map_apply(d.tile_dst, t);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) tile[i + (i >> 5)] = src[bs + map_apply(d.rd, i)];
+        __syncthreads();
+        for (int w = threadIdx.x; w < n; w += blockDim.x) {
+            const int l = (int)map_apply(d.wr_lds, w);
+            dst[bd + map_apply(d.wr_dst, w)] = tile[l + (l >> 5)];
+        }
+        __syncthreads();
+    }
+}
+
+void launch_permute(const PermDesc &d, const float2 *src, float2 *dst, hipStream_t s) {
+    int64_t blocks = d.n_tiles;
+    if (blocks > 256 * 32) blocks = 256 * 32;
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s, d, src, dst);
+}
+
+// ------------------------------------------------------------------ complex GEMM, FP32 MFMA
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Block tile BM x BN complex outputs, BK complex k per stage, 4 waves in a
+// 2 x 2 grid, each wave (BM/2) x (BN/2) as 32 x 32 MFMA blocks.  Operands are
+// staged de-interleaved (separate re / im planes) in LDS, double buffered.
+// C_re += A_re B_re + (-A_im) B_im ; C_im += A_re B_im + A_im B_re.
+template <int BM, int BN, int A_KFAST, int B_NFAST>
+__global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
+    constexpr int BK = 8;
+    constexpr int PAD = 4;
+    constexpr int WM = BM / 64, WN = BN / 64; // 32x32 blocks per wave
+    constexpr int EA = BM * BK / 256, EB = BN * BK / 256; // complex per thread per stage
+    __shared__ float As[2][2][BK][BM + PAD];
+    __shared__ float Bs[2][2][BK][BN + PAD];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t ntn = g.N / BN, ntm = g.M / BM;
+    const int64_t bid = blockIdx.x;
+    const int64_t bz = bid / (ntn * ntm);
+    const int64_t m0 = ((bid / ntn) % ntm) * BM, n0 = (bid % ntn) * BN;
+    const float2 *A = g.A + bz * g.sa;
+    const float2 *B = g.B + bz * g.sb;
+    float2 *C = g.C + bz * g.sc;
+    const int64_t M = g.M, N = g.N, K = g.K;
+
+    // per-thread global coordinates of its operand chunk
+    int a_r, a_c, b_r, b_c; // A: (m or k row, offset), B likewise
+    if (A_KFAST) { a_r = tid / (BK / EA); a_c = (tid % (BK / EA)) * EA; }      // m, k
+    else { a_r = tid / (BM / EA); a_c = (tid % (BM / EA)) * EA; }              // k, m
+    if (B_NFAST) { b_r = tid / (BN / EB); b_c = (tid % (BN / EB)) * EB; }      // k, n
+    else { b_r = tid / (BK / EB); b_c = (tid % (BK / EB)) * EB; }              // n, k
+
+    float2 ra[EA], rb[EB];
+    auto gload = [&](int64_t k0) {
+        const float2 *pa = A_KFAST ? A + (m0 + a_r) * K + k0 + a_c : A + (k0 + a_r) * M + m0 + a_c;
+        const float2 *pb = B_NFAST ? B + (k0 + b_r) * N + n0 + b_c : B + (n0 + b_r) * K + k0 + b_c;
+#pragma unroll
+        for (int e = 0; e < EA; e += 2) {
+            float4 v = *reinterpret_cast<const float4 *>(pa + e);
+            ra[e] = make_float2(v.x, v.y);
+            ra[e + 1] = make_float2(v.z, v.w);
+        }
+#pragma unroll
+        for (int e = 0; e < EB; e += 2) {
+            float4 v = *reinterpret_cast<const float4 *>(pb + e);
+            rb[e] = make_float2(v.x, v.y);
+            rb[e + 1] = make_float2(v.z, v.w);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < EA; e++) {
+            int kk = A_KFAST ? a_c + e : a_r, mm = A_KFAST ? a_r : a_c + e;
+            As[buf][0][kk][mm] = ra[e].x;
+            As[buf][1][kk][mm] = ra[e].y;
+        }
+#pragma unroll
+        for (int e = 0; e < EB; e++) {
+            int kk = B_NFAST ? b_r : b_c + e, nn = B_NFAST ? b_c + e : b_r;
+            Bs[buf][0][kk][nn] = rb[e].x;
+            Bs[buf][1][kk][nn] = rb[e].y;
+        }
+    };
+
+    floatx16 cre[WM][WN], cim[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; i++)
+#pragma unroll
+        for (int j = 0; j < WN; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) cre[i][j][v] = 0.f, cim[i][j][v] = 0.f;
+
+    const int nk = (int)(K / BK);
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt++) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 2) {
+            const int kr = kk + (lane >> 5);
+            float are[WM], aim[WM], anim[WM], bre[WN], bim[WN];
+#pragma unroll
+            for (int i = 0; i < WM; i++) {
+                const int mm = wm * (BM / 2) + i * 32 + (lane & 31);
+                are[i] = As[cur][0][kr][mm];
+                aim[i] = As[cur][1][kr][mm];
+                anim[i] = -aim[i];
+            }
+#pragma unroll
+            for (int j = 0; j < WN; j++) {
+                const int nn = wn * (BN / 2) + j * 32 + (lane & 31);
+                bre[j] = Bs[cur][0][kr][nn];
+                bim[j] = Bs[cur][1][kr][nn];
+            }
+#pragma unroll
+            for (int i = 0; i < WM; i++)
+#pragma unroll
+                for (int j = 0; j < WN; j++) {
+                    cre[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[i], bre[j], cre[i][j], 0, 0, 0);
+                    cre[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(anim[i], bim[j], cre[i][j], 0, 0, 0);
+                    cim[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[i], bim[j], cim[i][j], 0, 0, 0);
+                    cim[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[i], bre[j], cim[i][j], 0, 0, 0);
+                }
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    // epilogue: 32x32 accumulator, lane holds column lane%32 and rows
+    // 8*(v/4) + 4*(lane/32) + v%4
+#pragma unroll
+    for (int i = 0; i < WM; i++)
+#pragma unroll
+        for (int j = 0; j < WN; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int64_t m = m0 + wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int64_t n = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
+                C[m * N + n] = make_float2(cre[i][j][v], cim[i][j][v]);
+            }
+}
+
+template <int BM, int BN>
+static void gemm_dispatch(const GemmArgs &g, hipStream_t s) {
+    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch));
+    if (g.a_kfast && g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 1>), grid, dim3(256), 0, s, g);
+    else if (g.a_kfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 0>), grid, dim3(256), 0, s, g);
+    else if (g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 1>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 0>), grid, dim3(256), 0, s, g);
+}
+
+void launch_gemm(const GemmArgs &g, int precision, hipStream_t s) {
+    (void)precision;
+    if (g.M >= 128 && g.N >= 128) gemm_dispatch<128, 128>(g, s);
+    else if (g.M >= 128) gemm_dispatch<128, 64>(g, s);
+    else if (g.N >= 128) gemm_dispatch<64, 128>(g, s);
+    else gemm_dispatch<64, 64>(g, s);
+}
+
+// ------------------------------------------------------------------ FP64 accumulation
+__global__ void __launch_bounds__(256) k_accumulate(const float2 *__restrict__ root, BitMap om, BitMap sm, int64_t n,
+                                                    int64_t ns, double2 *__restrict__ acc) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int64_t ox = map_apply(om, x);
+    double2 a = acc[x];
+    for (int64_t s = 0; s < ns; s++) {
+        const float2 c = root[ox + map_apply(sm, s)];
+        a.x += (double)c.x;
+        a.y += (double)c.y;
+    }
+    acc[x] = a;
+}
+
+void launch_accumulate(const float2 *root, const BitMap &open_map, const BitMap &slice_map, int n_open,
+                       int n_batched, double2 *acc, hipStream_t s) {
+    const int64_t n = (int64_t)1 << n_open, ns = (int64_t)1 << n_batched;
+    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, root, open_map, slice_map,
+                       n, ns, acc);
+}
+
+__global__ void k_zero(double2 *p, int64_t n) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) p[x] = make_double2(0.0, 0.0);
+}
+
+void launch_zero(double2 *acc, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, acc, n);
+}
+
+__global__ void k_finalize(const double2 *__restrict__ acc, int64_t n, double scale, float2 *__restrict__ out,
+                           double2 *__restrict__ out64) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const double2 a = acc[x];
+    const double re = a.x * scale, im = a.y * scale;
+    out[x] = make_float2((float)re, (float)im);
+    if (out64) out64[x] = make_double2(re, im);
+}
+
+void launch_finalize(const double2 *acc, int64_t n, double scale, float2 *out, double2 *out64, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, acc, n, scale, out, out64);
+}
+
+} // namespace rqc

@@ -1,0 +1,574 @@
+// Lowering of a sliced contraction tree to a launch program.
+//
+// Tensors are complex64 arrays over binary legs; a layout is the list of legs
+// from the least significant bit of the element index upwards.  Steps are
+// lowered three ways:
+//   - subtrees whose tensors all have at most 2^kSmallLog elements run fused,
+//     one workgroup per subtree, with their intermediates in LDS (OP_SMALL);
+//   - steps with a short contracted dimension, or a thin free dimension, run
+//     as a streaming contraction that reads each operand element in place
+//     through bit maps (OP_STREAM, bound by HBM bandwidth);
+//   - the rest are complex GEMMs on MFMA (OP_GEMM), with operands permuted
+//     (OP_PERMUTE) into [batch][rows][cols] form when their layout does not
+//     already have it.
+// Intermediate buffers share one arena whose offsets come from a first-fit
+// plan over their lifetimes.
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <numeric>
+
+#include "host.hpp"
+
+namespace rqc {
+
+static constexpr int kSmallLog = 10;     // largest tensor inside a fused subtree
+static constexpr int kLdsBudget = 4096;  // complex64 elements of LDS per fused subtree
+static constexpr int kAlign = 64;        // arena alignment in elements (512 bytes)
+
+BitMap make_map(const std::vector<int> &l2m) {
+    BitMap m;
+    int i = 0;
+    const int n = (int)l2m.size();
+    while (i < n) {
+        if (l2m[i] < 0) {
+            i++;
+            continue;
+        }
+        int j = i + 1;
+        while (j < n && l2m[j] == l2m[j - 1] + 1) j++;
+        if (m.n >= kMaxRuns) fail(RQC_EPLAN, "bit map has too many runs");
+        m.src[m.n] = (uint8_t)i;
+        m.len[m.n] = (uint8_t)(j - i);
+        m.dst[m.n] = (uint8_t)l2m[i];
+        m.n++;
+        i = j;
+    }
+    return m;
+}
+
+static int pos_in(const std::vector<int> &layout, int v) {
+    for (size_t i = 0; i < layout.size(); i++)
+        if (layout[i] == v) return (int)i;
+    return -1;
+}
+
+static bool contains(const Legs &s, int v) { return std::binary_search(s.begin(), s.end(), v); }
+
+// Does `layout` consist of the groups g0, g1, g2 (as sets), in that order from bit 0?
+static bool fits3(const std::vector<int> &layout, const Legs &g0, const Legs &g1, const Legs &g2) {
+    size_t i = 0;
+    for (const Legs *g : {&g0, &g1, &g2}) {
+        for (size_t k = 0; k < g->size(); k++, i++)
+            if (i >= layout.size() || !contains(*g, layout[i])) return false;
+    }
+    return i == layout.size();
+}
+
+static std::vector<int> ordered_subset(const std::vector<int> &layout, const Legs &set) {
+    std::vector<int> out;
+    for (int v : layout)
+        if (contains(set, v)) out.push_back(v);
+    return out;
+}
+
+static Legs set_of(std::vector<int> v) {
+    std::sort(v.begin(), v.end());
+    return v;
+}
+
+struct Lowerer {
+    const Tree &tree;
+    const std::vector<Legs> &legs;
+    Program &prog;
+    int nt;
+    std::vector<std::vector<int>> layout;
+    std::vector<Buf> where;        // location of each tensor once materialised
+    std::vector<int> parent;
+    std::vector<char> sub_small;   // whole subtree is small-eligible
+    std::vector<char> in_small;    // step executed inside a fused subtree (not its root)
+    // arena buffers
+    struct Alloc {
+        int64_t size;
+        int first, last; // op indices of production and last use
+        int64_t off = -1;
+    };
+    std::vector<Alloc> allocs;
+    std::vector<int> tensor_alloc; // tensor -> alloc index (-1 none)
+    std::vector<int> op_first_use;
+    int op_counter = 0;
+
+    Lowerer(const Tree &t, const std::vector<Legs> &l, Program &p) : tree(t), legs(l), prog(p) {
+        nt = t.n_leaves + (int)t.steps.size();
+        layout.resize(nt);
+        where.resize(nt);
+        parent.assign(nt, -1);
+        tensor_alloc.assign(nt, -1);
+        for (size_t s = 0; s < t.steps.size(); s++) {
+            parent[t.steps[s].first] = t.n_leaves + (int)s;
+            parent[t.steps[s].second] = t.n_leaves + (int)s;
+        }
+    }
+
+    int64_t size_of(int t) const { return (int64_t)1 << legs[t].size(); }
+
+    int new_alloc(int64_t size, int tensor) {
+        allocs.push_back({size, op_counter, op_counter});
+        if (tensor >= 0) tensor_alloc[tensor] = (int)allocs.size() - 1;
+        return (int)allocs.size() - 1;
+    }
+    void touch(int alloc) {
+        if (alloc >= 0) allocs[alloc].last = std::max(allocs[alloc].last, op_counter);
+    }
+
+    // ---------------------------------------------------------------- small subtrees
+    // Emit the steps of the subtree rooted at t (post-order) into prog.small_steps.
+    // Returns the LDS offset of the result (or -1 when it is a leaf).  `lds_used`
+    // tracks a simple free list over LDS.
+    struct Lds {
+        std::vector<std::pair<int, int>> blocks; // (offset, size) in use
+        int peak = 0;
+        int alloc(int size) {
+            std::sort(blocks.begin(), blocks.end());
+            int off = 0;
+            for (auto &b : blocks) {
+                if (b.first - off >= size) break;
+                off = std::max(off, b.first + b.second);
+            }
+            blocks.push_back({off, size});
+            peak = std::max(peak, off + size);
+            return off;
+        }
+        void release(int off) {
+            for (size_t i = 0; i < blocks.size(); i++)
+                if (blocks[i].first == off) {
+                    blocks.erase(blocks.begin() + i);
+                    return;
+                }
+        }
+    };
+
+    int subtree_peak(int t) {
+        // LDS elements needed to evaluate t's subtree in post-order (larger child first)
+        if (t < tree.n_leaves) return 0;
+        auto [a, b] = tree.steps[t - tree.n_leaves];
+        int pa = subtree_peak(a), pb = subtree_peak(b);
+        int sa = a < tree.n_leaves ? 0 : (int)size_of(a);
+        int sb = b < tree.n_leaves ? 0 : (int)size_of(b);
+        int first = std::max(pa, pb + sa);
+        int second = std::max(pb, pa + sb);
+        int kids = std::min(first, second);
+        return std::max(kids, sa + sb + (int)size_of(t));
+    }
+
+    void emit_small_step(int t, int a_kind, int64_t a_off, int b_kind, int64_t b_off, int c_kind,
+                         int64_t c_off) {
+        auto [a, b] = tree.steps[t - tree.n_leaves];
+        const Legs &C = legs[t];
+        std::vector<int> &LA = layout[a], &LB = layout[b];
+        // C layout: A's surviving legs in A order, then B's new legs in B order
+        std::vector<int> LC;
+        for (int v : LA)
+            if (contains(C, v)) LC.push_back(v);
+        for (int v : LB)
+            if (contains(C, v) && pos_in(LA, v) < 0) LC.push_back(v);
+        layout[t] = LC;
+        std::vector<int> con;
+        for (int v : LA)
+            if (!contains(C, v) && pos_in(LB, v) >= 0) con.push_back(v);
+        SmallStep st;
+        st.a_kind = a_kind;
+        st.b_kind = b_kind;
+        st.c_kind = c_kind;
+        st.a_off = a_off;
+        st.b_off = b_off;
+        st.c_off = c_off;
+        st.rc = (int)LC.size();
+        st.kc = (int)con.size();
+        std::vector<int> ax(LC.size()), bx(LC.size()), ay(con.size()), by(con.size());
+        for (size_t j = 0; j < LC.size(); j++) ax[j] = pos_in(LA, LC[j]), bx[j] = pos_in(LB, LC[j]);
+        for (size_t j = 0; j < con.size(); j++) ay[j] = pos_in(LA, con[j]), by[j] = pos_in(LB, con[j]);
+        st.ax = make_map(ax);
+        st.bx = make_map(bx);
+        st.ay = make_map(ay);
+        st.by = make_map(by);
+        prog.small_steps.push_back(st);
+        double f = 8.0 * std::exp2((double)(LC.size() + con.size()));
+        prog.flops += f;
+    }
+
+    // returns (kind, offset) of where t's value sits during the subtree program
+    std::pair<int, int64_t> eval_small(int t, Lds &lds, bool is_root) {
+        if (t < tree.n_leaves) return {1, where[t].off};
+        auto [a, b] = tree.steps[t - tree.n_leaves];
+        int pa = subtree_peak(a), pb = subtree_peak(b);
+        int sa = a < tree.n_leaves ? 0 : (int)size_of(a);
+        int sb = b < tree.n_leaves ? 0 : (int)size_of(b);
+        bool a_first = std::max(pa, pb + sa) <= std::max(pb, pa + sb);
+        std::pair<int, int64_t> ra, rb;
+        if (a_first) {
+            ra = eval_small(a, lds, false);
+            rb = eval_small(b, lds, false);
+        } else {
+            rb = eval_small(b, lds, false);
+            ra = eval_small(a, lds, false);
+        }
+        int ck;
+        int64_t co;
+        if (is_root) {
+            ck = 2;
+            co = -1; // patched once the arena buffer exists
+        } else {
+            ck = 0;
+            co = lds.alloc((int)size_of(t));
+        }
+        emit_small_step(t, ra.first, ra.second, rb.first, rb.second, ck, co);
+        if (ra.first == 0) lds.release((int)ra.second);
+        if (rb.first == 0) lds.release((int)rb.second);
+        return {ck, co};
+    }
+
+    void mark_sub_small() {
+        sub_small.assign(nt, 0);
+        for (int i = 0; i < tree.n_leaves; i++) sub_small[i] = legs[i].size() <= (size_t)kSmallLog;
+        for (size_t s = 0; s < tree.steps.size(); s++) {
+            int t = tree.n_leaves + (int)s;
+            auto [a, b] = tree.steps[s];
+            sub_small[t] = sub_small[a] && sub_small[b] && legs[t].size() <= (size_t)kSmallLog;
+        }
+        // enforce the LDS budget: a small subtree too big for LDS is cut below
+        for (int t = nt - 1; t >= tree.n_leaves; t--) {
+            if (!sub_small[t]) continue;
+            bool root = parent[t] < 0 || !sub_small[parent[t]];
+            if (root && subtree_peak(t) > kLdsBudget) {
+                // evaluate the children as their own fused subtrees
+                sub_small[t] = 0;
+            }
+        }
+        // repeat until stable (cutting a node exposes its children as roots)
+        bool changed = true;
+        while (changed) {
+            changed = false;
+            for (int t = nt - 1; t >= tree.n_leaves; t--) {
+                if (!sub_small[t]) continue;
+                bool root = parent[t] < 0 || !sub_small[parent[t]];
+                if (root && subtree_peak(t) > kLdsBudget) {
+                    sub_small[t] = 0;
+                    changed = true;
+                }
+            }
+        }
+    }
+
+    // ---------------------------------------------------------------- phase-2 steps
+    Buf buf_of(int t) { return where[t]; }
+
+    void use_tensor(int t) {
+        if (tensor_alloc[t] >= 0) touch(tensor_alloc[t]);
+    }
+
+    Buf materialise(int t) {
+        int al = new_alloc(size_of(t), t);
+        Buf b;
+        b.kind = 0;
+        b.off = al; // resolved to an element offset after the arena plan
+        where[t] = b;
+        return b;
+    }
+
+    void emit_stream(int t) {
+        auto [a, b] = tree.steps[t - tree.n_leaves];
+        if (size_of(b) > size_of(a)) std::swap(a, b);
+        const Legs &C = legs[t];
+        const std::vector<int> &LA = layout[a], &LB = layout[b];
+        std::vector<int> newb;
+        for (int v : LB)
+            if (contains(C, v) && pos_in(LA, v) < 0) newb.push_back(v);
+        std::vector<int> LC;
+        size_t nb = 0;
+        std::vector<int> con;
+        for (int v : LA) {
+            if (contains(C, v))
+                LC.push_back(v);
+            else {
+                con.push_back(v);
+                if (nb < newb.size()) LC.push_back(newb[nb++]);
+            }
+        }
+        for (; nb < newb.size(); nb++) LC.push_back(newb[nb]);
+        layout[t] = LC;
+        StreamOp op;
+        op.a = buf_of(a);
+        op.b = buf_of(b);
+        use_tensor(a);
+        use_tensor(b);
+        op.c = materialise(t);
+        op.rc = (int)LC.size();
+        op.kc = (int)con.size();
+        std::vector<int> ax(LC.size()), bx(LC.size()), ay(con.size()), by(con.size());
+        for (size_t j = 0; j < LC.size(); j++) ax[j] = pos_in(LA, LC[j]), bx[j] = pos_in(LB, LC[j]);
+        for (size_t j = 0; j < con.size(); j++) ay[j] = pos_in(LA, con[j]), by[j] = pos_in(LB, con[j]);
+        op.ax = make_map(ax);
+        op.bx = make_map(bx);
+        op.ay = make_map(ay);
+        op.by = make_map(by);
+        double f = 8.0 * std::exp2((double)(LC.size() + con.size()));
+        double by_ = 8.0 * (double)(size_of(a) + size_of(b) + size_of(t));
+        prog.streams.push_back(op);
+        prog.ops.push_back({OP_STREAM, (int)prog.streams.size() - 1, f, by_});
+        prog.flops += f;
+        prog.bytes += by_;
+        op_counter++;
+    }
+
+    // permute tensor t into `target` layout; returns the new buffer
+    Buf emit_permute(int t, const std::vector<int> &target) {
+        PermuteOp op;
+        op.src = buf_of(t);
+        use_tensor(t);
+        op.r = (int)target.size();
+        op.perm.resize(op.r);
+        for (int i = 0; i < op.r; i++) op.perm[i] = pos_in(target, layout[t][i]);
+        int al = new_alloc(size_of(t), -1);
+        op.dst.kind = 0;
+        op.dst.off = al;
+        double by_ = 16.0 * (double)size_of(t);
+        prog.permutes.push_back(op);
+        prog.ops.push_back({OP_PERMUTE, (int)prog.permutes.size() - 1, 0.0, by_});
+        prog.bytes += by_;
+        op_counter++;
+        perm_alloc_last = al;
+        return op.dst;
+    }
+    int perm_alloc_last = -1;
+
+    void emit_gemm(int t) {
+        auto [a, b] = tree.steps[t - tree.n_leaves];
+        const Legs &A = legs[a], &B = legs[b], &C = legs[t];
+        Legs batch, con, fa, fb;
+        for (int v : A) {
+            bool inb = contains(B, v), inc = contains(C, v);
+            if (inb && inc) batch.push_back(v);
+            else if (inb) con.push_back(v);
+            else if (inc) fa.push_back(v);
+            else fail(RQC_EPLAN, "leg summed within one operand");
+        }
+        for (int v : B)
+            if (!contains(A, v)) {
+                if (contains(C, v)) fb.push_back(v);
+                else fail(RQC_EPLAN, "leg summed within one operand");
+            }
+        const std::vector<int> &LA = layout[a], &LB = layout[b];
+        // A view
+        int a_kfast;
+        std::vector<int> kord, bord, faord, fbord;
+        bool a_ok = true;
+        if (fits3(LA, con, fa, batch)) a_kfast = 1;
+        else if (fits3(LA, fa, con, batch)) a_kfast = 0;
+        else a_ok = false, a_kfast = 1;
+        kord = ordered_subset(LA, con);
+        bord = ordered_subset(LA, batch);
+        faord = ordered_subset(LA, fa);
+        fbord = ordered_subset(LB, fb);
+        // B view with A's K and batch orders
+        auto b_layout = [&](int nfast) {
+            std::vector<int> L;
+            if (nfast) {
+                L = fbord;
+                L.insert(L.end(), kord.begin(), kord.end());
+            } else {
+                L = kord;
+                L.insert(L.end(), fbord.begin(), fbord.end());
+            }
+            L.insert(L.end(), bord.begin(), bord.end());
+            return L;
+        };
+        int b_nfast = -1;
+        if (LB == b_layout(1)) b_nfast = 1;
+        else if (LB == b_layout(0)) b_nfast = 0;
+        // If B fits its own groups but in a different K/batch order, consider
+        // permuting A to B's orders instead when A is the smaller tensor.
+        if (b_nfast < 0 && size_of(a) < size_of(b)) {
+            bool bk = fits3(LB, fb, con, batch), bn = fits3(LB, con, fb, batch);
+            if (bk || bn) {
+                kord = ordered_subset(LB, con);
+                bord = ordered_subset(LB, batch);
+                b_nfast = bk ? 1 : 0;
+                a_ok = false; // A will be permuted to match
+                a_kfast = 1;
+            }
+        }
+        Buf abuf = buf_of(a), bbuf = buf_of(b);
+        int a_tmp = -1, b_tmp = -1;
+        std::vector<int> LAt;
+        if (a_kfast) {
+            LAt = kord;
+            LAt.insert(LAt.end(), faord.begin(), faord.end());
+        } else {
+            LAt = faord;
+            LAt.insert(LAt.end(), kord.begin(), kord.end());
+        }
+        LAt.insert(LAt.end(), bord.begin(), bord.end());
+        if (!a_ok || LAt != LA) {
+            abuf = emit_permute(a, LAt);
+            a_tmp = perm_alloc_last;
+        }
+        if (b_nfast < 0) {
+            b_nfast = 1;
+            bbuf = emit_permute(b, b_layout(1));
+            b_tmp = perm_alloc_last;
+        }
+        GemmOp g;
+        g.a = abuf;
+        g.b = bbuf;
+        use_tensor(a);
+        use_tensor(b);
+        if (a_tmp >= 0) touch(a_tmp);
+        if (b_tmp >= 0) touch(b_tmp);
+        g.batch = (int64_t)1 << batch.size();
+        g.M = (int64_t)1 << fa.size();
+        g.N = (int64_t)1 << fb.size();
+        g.K = (int64_t)1 << con.size();
+        g.a_kfast = a_kfast;
+        g.b_nfast = b_nfast;
+        g.c_nfast = 1;
+        g.sa = g.M * g.K;
+        g.sb = g.K * g.N;
+        g.sc = g.M * g.N;
+        std::vector<int> LC = fbord;
+        LC.insert(LC.end(), faord.begin(), faord.end());
+        LC.insert(LC.end(), bord.begin(), bord.end());
+        layout[t] = LC;
+        g.c = materialise(t);
+        if (a_tmp >= 0) touch(a_tmp);
+        if (b_tmp >= 0) touch(b_tmp);
+        double f = 8.0 * (double)g.batch * (double)g.M * (double)g.N * (double)g.K;
+        double by_ = 8.0 * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
+        prog.gemms.push_back(g);
+        prog.ops.push_back({OP_GEMM, (int)prog.gemms.size() - 1, f, by_});
+        prog.flops += f;
+        prog.gemm_flops += f;
+        prog.bytes += by_;
+        op_counter++;
+    }
+
+    bool gemm_worthy(int t) {
+        auto [a, b] = tree.steps[t - tree.n_leaves];
+        const Legs &A = legs[a], &B = legs[b], &C = legs[t];
+        int nb = 0, nk = 0, nfa = 0, nfb = 0;
+        for (int v : A) {
+            bool inb = contains(B, v), inc = contains(C, v);
+            if (inb && inc) nb++;
+            else if (inb) nk++;
+            else nfa++;
+        }
+        for (int v : B)
+            if (!contains(A, v)) nfb++;
+        (void)nb;
+        return nk >= 3 && nfa >= 6 && nfb >= 6;
+    }
+
+    void run(const std::vector<int> &leaf_offsets) {
+        for (int i = 0; i < tree.n_leaves; i++) {
+            layout[i] = legs[i]; // sorted, as produced by the leaf-select kernel
+            where[i].kind = 1;
+            where[i].off = leaf_offsets[i];
+        }
+        mark_sub_small();
+        // fused small subtrees: roots are small steps whose parent is not small
+        in_small.assign(nt, 0);
+        for (int t = tree.n_leaves; t < nt; t++) {
+            if (!sub_small[t]) continue;
+            bool root = parent[t] < 0 || !sub_small[parent[t]];
+            if (!root) continue;
+            Lds lds;
+            int first = (int)prog.small_steps.size();
+            eval_small(t, lds, true);
+            SmallTree st;
+            st.first_step = first;
+            st.n_steps = (int)prog.small_steps.size() - first;
+            prog.small_trees.push_back(st);
+            prog.small_lds_elems = std::max(prog.small_lds_elems, lds.peak);
+            Buf out = materialise(t);
+            prog.small_steps.back().c_off = out.off; // alloc index, resolved below
+            // mark inner steps
+            std::function<void(int)> mark = [&](int u) {
+                if (u < tree.n_leaves) return;
+                in_small[u] = 1;
+                mark(tree.steps[u - tree.n_leaves].first);
+                mark(tree.steps[u - tree.n_leaves].second);
+            };
+            mark(t);
+        }
+        if (!prog.small_trees.empty()) {
+            double by_ = 0;
+            for (auto &s : prog.small_trees) {
+                (void)s;
+            }
+            prog.ops.push_back({OP_SMALL, 0, 0.0, by_});
+            op_counter++;
+        }
+        // remaining steps in tree order
+        for (int t = tree.n_leaves; t < nt; t++) {
+            if (in_small[t]) continue;
+            if (gemm_worthy(t)) emit_gemm(t);
+            else emit_stream(t);
+        }
+        int root = tree.root();
+        use_tensor(root);
+        op_counter++;
+        // arena plan: first fit by decreasing size over lifetime overlaps
+        std::vector<int> order(allocs.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int x, int y) {
+            return allocs[x].size != allocs[y].size ? allocs[x].size > allocs[y].size : x < y;
+        });
+        std::vector<int> placed;
+        int64_t extent = 0;
+        for (int i : order) {
+            Alloc &al = allocs[i];
+            int64_t sz = (al.size + kAlign - 1) / kAlign * kAlign;
+            std::vector<std::pair<int64_t, int64_t>> busy;
+            for (int j : placed) {
+                const Alloc &o = allocs[j];
+                if (o.first <= al.last && al.first <= o.last)
+                    busy.push_back({o.off, o.off + (o.size + kAlign - 1) / kAlign * kAlign});
+            }
+            std::sort(busy.begin(), busy.end());
+            int64_t off = 0;
+            for (auto &b : busy) {
+                if (b.first - off >= sz) break;
+                off = std::max(off, b.second);
+            }
+            al.off = off;
+            extent = std::max(extent, off + sz);
+            placed.push_back(i);
+        }
+        prog.arena_elems = extent;
+        auto fix = [&](Buf &b) {
+            if (b.kind == 0) b.off = allocs[b.off].off;
+        };
+        for (auto &s : prog.small_steps)
+            if (s.c_kind == 2) s.c_off = allocs[s.c_off].off;
+        for (auto &s : prog.streams) fix(s.a), fix(s.b), fix(s.c);
+        for (auto &p : prog.permutes) fix(p.src), fix(p.dst);
+        for (auto &g : prog.gemms) fix(g.a), fix(g.b), fix(g.c);
+        for (int t = 0; t < nt; t++)
+            if (where[t].kind == 0 && tensor_alloc[t] >= 0) where[t].off = allocs[tensor_alloc[t]].off;
+        prog.root = where[root];
+        for (int t = 0; t < nt; t++) prog.max_log2 = std::max(prog.max_log2, (int)legs[t].size());
+    }
+};
+
+// Lower the tree.  leaf_offsets: element offset of each projected leaf in the
+// leaf buffer.  Returns the root layout through `root_layout`.
+Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
+                   std::vector<int> &root_layout) {
+    Program prog;
+    Lowerer L(tree, legs, prog);
+    L.run(leaf_offsets);
+    root_layout = L.layout[tree.root()];
+    return prog;
+}
+
+} // namespace rqc

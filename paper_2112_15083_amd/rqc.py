@@ -1,0 +1,275 @@
+"""ctypes binding of librqc (include/rqc.h): argument marshalling only.
+
+Every function has the name of its C entry point without the ``rqc_`` prefix.
+Device buffers are passed as torch tensors (their data_ptr) or raw integer
+addresses; streams as torch.cuda.Stream objects, raw handles, or None for the
+current torch stream.  A non-OK status raises RqcError carrying the library's
+message.  The library must be built (python -m paper_2112_15083_amd.build);
+importing this module without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librqc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"librqc.so is not built ({LIB_PATH}); run python -m paper_2112_15083_amd.build")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, EPARSE, EPLAN, ENOMEM, EDEVICE, ESHORT = 0, -1, -2, -3, -4, -5, -6
+C64, BF16X3, FP16X3 = 0, 1, 2
+K_LEAF, K_SMALL, K_STREAM, K_PERMUTE, K_GEMM, K_ACCUM, K_FINAL, K_SAMPLE = range(8)
+K_NAMES = ["leaf_select", "small_trees", "stream", "permute", "gemm", "accumulate", "finalize", "sample"]
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("max_log2_tensor", ctypes.c_int32), ("n_sliced_target", ctypes.c_int32),
+                ("max_log2_batched", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("target_fidelity", ctypes.c_double), ("partial_k", ctypes.c_int32),
+                ("partial_count", ctypes.c_int32), ("path_trials", ctypes.c_int32),
+                ("path_seed", ctypes.c_uint64), ("profile", ctypes.c_int32), ("dry_run", ctypes.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_open", ctypes.c_int32), ("n_variables", ctypes.c_int32),
+                ("n_sliced", ctypes.c_int32), ("n_batched", ctypes.c_int32), ("n_partial", ctypes.c_int32),
+                ("n_slices", ctypes.c_int64), ("n_partial_kept", ctypes.c_int64), ("fidelity", ctypes.c_double),
+                ("flops_per_batch", ctypes.c_double), ("flops_unsliced", ctypes.c_double),
+                ("gemm_flop_share", ctypes.c_double), ("bytes_per_batch", ctypes.c_double),
+                ("max_log2_tensor", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("n_launches", ctypes.c_int32), ("n_groups", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SampleStats(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int64), ("batches", ctypes.c_int64), ("batches_used", ctypes.c_int64),
+                ("eps_J", ctypes.c_double), ("p_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("seconds", ctypes.c_double * 8),
+                ("flops", ctypes.c_double * 8), ("bytes", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return {K_NAMES[i]: dict(launches=self.launches[i], seconds=self.seconds[i], flops=self.flops[i],
+                                 bytes=self.bytes[i]) for i in range(8)}
+
+
+_P = ctypes.c_void_p
+_sig = {
+    "rqc_load_circuit": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_P)],
+    "rqc_circuit_info": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32)],
+    "rqc_plan_create": [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32,
+                        ctypes.POINTER(PlanOpts), ctypes.POINTER(_P)],
+    "rqc_plan_info": [_P, ctypes.POINTER(PlanInfo)],
+    "rqc_plan_sliced_legs": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "rqc_plan_partial": [_P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int64],
+    "rqc_plan_profile": [_P, ctypes.POINTER(Profile)],
+    "rqc_plan_profile_reset": [_P],
+    "rqc_contract_amplitudes": [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P],
+    "rqc_rejection_sample": [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                             ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(SampleStats), _P],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.rqc_last_error.restype = ctypes.c_char_p
+_lib.rqc_version.restype = ctypes.c_char_p
+_lib.rqc_plan_destroy.argtypes = [_P]
+_lib.rqc_plan_destroy.restype = None
+_lib.rqc_circuit_destroy.argtypes = [_P]
+_lib.rqc_circuit_destroy.restype = None
+
+EXPORTS = sorted(list(_sig) + ["rqc_last_error", "rqc_version", "rqc_plan_destroy", "rqc_circuit_destroy"])
+
+
+class RqcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"librqc status {status}: {msg}")
+        self.status = status
+
+
+def last_error() -> str:
+    return _lib.rqc_last_error().decode()
+
+
+def version() -> str:
+    return _lib.rqc_version().decode()
+
+
+def _check(st, allow=()):
+    if st != OK and st not in allow:
+        raise RqcError(st, last_error())
+    return st
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, numpy array, int or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _i32(seq):
+    arr = (ctypes.c_int32 * max(1, len(seq)))(*seq)
+    return arr
+
+
+def _u64(seq):
+    return (ctypes.c_uint64 * max(1, len(seq)))(*[int(v) & (2 ** 64 - 1) for v in seq])
+
+
+class Circuit:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.rqc_circuit_destroy(self.handle)
+            self.handle = None
+
+
+class Plan:
+    def __init__(self, handle, open_qubits):
+        self.handle = handle
+        self.open_qubits = list(open_qubits)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.rqc_plan_destroy(self.handle)
+            self.handle = None
+
+
+def load_circuit(text: str) -> Circuit:
+    b = text.encode()
+    h = _P()
+    _check(_lib.rqc_load_circuit(b, len(b), ctypes.byref(h)))
+    return Circuit(h)
+
+
+def circuit_info(c: Circuit):
+    n, v, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.rqc_circuit_info(c.handle, ctypes.byref(n), ctypes.byref(v), ctypes.byref(g)))
+    return dict(n_qubits=n.value, n_variables=v.value, n_gates=g.value)
+
+
+def make_opts(**kw) -> PlanOpts:
+    o = PlanOpts()
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, v)
+    return o
+
+
+def plan_create(c: Circuit, open_qubits, path=None, sliced_legs=None, opts: PlanOpts | None = None,
+                **kw) -> Plan:
+    if opts is None:
+        opts = make_opts(**kw)
+    flat = [x for pr in path for x in pr] if path is not None else None
+    h = _P()
+    _check(_lib.rqc_plan_create(c.handle, _i32(flat) if flat is not None else None,
+                                len(path) if path is not None else 0,
+                                _i32(sliced_legs) if sliced_legs is not None else None,
+                                len(sliced_legs) if sliced_legs is not None else 0,
+                                _i32(list(open_qubits)), len(open_qubits), ctypes.byref(opts), ctypes.byref(h)))
+    return Plan(h, open_qubits)
+
+
+def plan_info(p: Plan) -> dict:
+    info = PlanInfo()
+    _check(_lib.rqc_plan_info(p.handle, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def plan_sliced_legs(p: Plan):
+    n = ctypes.c_int32()
+    _check(_lib.rqc_plan_sliced_legs(p.handle, None, 0, ctypes.byref(n)))
+    arr = (ctypes.c_int32 * max(1, n.value))()
+    _check(_lib.rqc_plan_sliced_legs(p.handle, arr, n.value, ctypes.byref(n)))
+    return list(arr)[: n.value]
+
+
+def plan_partial(p: Plan):
+    info = plan_info(p)
+    k, nx = info["n_partial"], info["n_partial_kept"]
+    S = (ctypes.c_int32 * max(1, k))()
+    X = (ctypes.c_uint64 * max(1, nx))()
+    nr = (1 << k) if k else 0
+    R = (ctypes.c_double * max(1, nr))()
+    _check(_lib.rqc_plan_partial(p.handle, S, k, X, nx, R, nr))
+    return list(S)[:k], list(X)[:nx], list(R)[:nr]
+
+
+def plan_profile(p: Plan) -> dict:
+    pr = Profile()
+    _check(_lib.rqc_plan_profile(p.handle, ctypes.byref(pr)))
+    return pr.as_dict()
+
+
+def plan_profile_reset(p: Plan):
+    _check(_lib.rqc_plan_profile_reset(p.handle))
+
+
+def contract_amplitudes(p: Plan, fixed_bits, out_amps, out_f64=None, slice_ids=None, stream=None):
+    fb = _u64(list(fixed_bits))
+    sl = _u64(list(slice_ids)) if slice_ids is not None else None
+    _check(_lib.rqc_contract_amplitudes(p.handle, sl, len(slice_ids) if slice_ids is not None else 0, fb,
+                                        len(fixed_bits), _ptr(out_amps), _ptr(out_f64), _stream(stream)))
+
+
+def rejection_sample(amps, fixed_bits, open_qubits, n_qubits, n_samples, out_samples, alpha=2.0, F_norm=1.0,
+                     seed=7, batch_index_base=0, log2_NA=6, pick_steps=0, stream=None):
+    """Returns (n_out, stats dict, status) -- status is OK or ESHORT."""
+    n_out = ctypes.c_int64()
+    st = SampleStats()
+    code = _check(_lib.rqc_rejection_sample(_ptr(amps), _u64(list(fixed_bits)), len(fixed_bits),
+                                            _i32(list(open_qubits)), len(open_qubits), log2_NA, n_qubits,
+                                            alpha, F_norm, seed, batch_index_base, pick_steps, n_samples,
+                                            _ptr(out_samples), ctypes.byref(n_out), ctypes.byref(st),
+                                            _stream(stream)), allow=(ESHORT,))
+    return n_out.value, st.as_dict(), code
+
+
+def plan_destroy(p: Plan):
+    if p.handle:
+        _lib.rqc_plan_destroy(p.handle)
+        p.handle = None
+
+
+def circuit_destroy(c: Circuit):
+    if c.handle:
+        _lib.rqc_circuit_destroy(c.handle)
+        c.handle = None

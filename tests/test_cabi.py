@@ -1,0 +1,103 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol, and
+its host-side planner (dry-run mode, no GPU) behaves as documented."""
+import os
+import re
+
+import pytest
+
+import synthetic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rqc():
+    from paper_2112_15083_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_2112_15083_amd import rqc as lib
+    return lib
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "rqc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rqc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(rqc):
+    import ctypes
+    lib = ctypes.CDLL(rqc.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(rqc.EXPORTS)
+
+
+def test_parse_errors_are_reported(rqc):
+    with pytest.raises(rqc.RqcError) as e:
+        rqc.load_circuit("qubits 2\nsx 0 5\n")
+    assert e.value.status == rqc.EPARSE
+    with pytest.raises(rqc.RqcError) as e:
+        rqc.load_circuit("qubits 2\nfoo 0 1\n")
+    assert "line 2" in str(e.value)
+    with pytest.raises(rqc.RqcError):
+        rqc.load_circuit("sx 0 0\n")
+
+
+def test_circuit_info_counts_variables(rqc):
+    t = synthetic.circuit_text(3, 4, 8, 0)
+    info = rqc.circuit_info(rqc.load_circuit(t))
+    # 12 inputs + one variable per single-qubit gate (fSim(pi/2) adds none)
+    assert info == dict(n_qubits=12, n_variables=12 + 12 * 8, n_gates=t.count("\nsx") + t.count("\nsy")
+                        + t.count("\nsw") + t.count("\nfsim"))
+
+
+def test_dry_run_plans(rqc):
+    for name, ns in (("tiny", 0), ("mid", 6)):
+        cfg = synthetic.CONFIGS[name]
+        t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+        p = rqc.plan_create(rqc.load_circuit(t), cfg["open_qubits"], dry_run=1, n_sliced_target=ns)
+        info = rqc.plan_info(p)
+        assert info["n_sliced"] == ns and info["n_slices"] == 1 << ns
+        assert info["n_open"] == len(cfg["open_qubits"])
+        assert info["flops_per_batch"] > 0
+        legs = rqc.plan_sliced_legs(p)
+        assert len(legs) == ns and len(set(legs)) == ns
+        # sliced legs are internal variables: not inputs, not outputs
+        assert all(v >= cfg["rows"] * cfg["cols"] for v in legs)
+
+
+def test_memory_target_slicing(rqc):
+    cfg = synthetic.CONFIGS["mid"]
+    t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"])
+    p = rqc.plan_create(rqc.load_circuit(t), cfg["open_qubits"], dry_run=1, max_log2_tensor=20,
+                        n_sliced_target=-1, max_log2_batched=20)
+    info = rqc.plan_info(p)
+    assert info["max_log2_tensor"] <= 20
+    assert info["n_sliced"] > 0
+
+
+def test_invalid_plan_arguments(rqc):
+    t = synthetic.circuit_text(3, 3, 4, 0)
+    c = rqc.load_circuit(t)
+    with pytest.raises(rqc.RqcError):
+        rqc.plan_create(c, [0, 0], dry_run=1)
+    with pytest.raises(rqc.RqcError):
+        rqc.plan_create(c, [9], dry_run=1)
+    with pytest.raises(rqc.RqcError):  # an input variable cannot be sliced
+        rqc.plan_create(c, [0], dry_run=1, sliced_legs=[0])
+    with pytest.raises(rqc.RqcError):  # a path that does not contract everything
+        rqc.plan_create(c, [0], dry_run=1, path=[(0, 1)])
+
+
+def test_user_path_and_legs_are_used(rqc):
+    t = synthetic.circuit_text(2, 2, 3, 0)
+    c = rqc.load_circuit(t)
+    n_g = rqc.circuit_info(c)["n_gates"]
+    # left-deep order over the gate tensors
+    path = [(0, 1)] + [(n_g + s, s + 2) for s in range(n_g - 2)]
+    p = rqc.plan_create(c, [0, 1], dry_run=1, path=path, sliced_legs=[5])
+    info = rqc.plan_info(p)
+    assert info["n_steps"] == n_g - 1 and rqc.plan_sliced_legs(p) == [5]

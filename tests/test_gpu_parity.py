@@ -1,0 +1,179 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Bar (complex64 path): relative L2 error <= 1e-5 per returned batch; samples
+bit-identical to the oracle's sampler for the same amplitudes and seed.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import sampler as osamp
+from oracle import sv as osv
+
+from gpu_common import circuit, oracle_batches, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rqc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_15083_amd import rqc as lib
+    return lib
+
+
+def run_amplitudes(rqc, text, open_qubits, fixed_list, **opts):
+    import torch
+    c = rqc.load_circuit(text)
+    p = rqc.plan_create(c, open_qubits, **opts)
+    out = torch.empty((len(fixed_list), 1 << len(open_qubits), 2), dtype=torch.float32, device="cuda")
+    out64 = torch.empty((len(fixed_list), 1 << len(open_qubits), 2), dtype=torch.float64, device="cuda")
+    rqc.contract_amplitudes(p, fixed_list, out, out64)
+    torch.cuda.synchronize()
+    a = out.cpu().numpy()
+    a64 = out64.cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1], a64[..., 0] + 1j * a64[..., 1], rqc.plan_info(p), p
+
+
+def test_tiny_all_open(rqc):
+    cfg = synthetic.CONFIGS["tiny"]
+    text = circuit(cfg["rows"], cfg["cols"], cfg["cycles"])
+    amps, amps64, info, _ = run_amplitudes(rqc, text, cfg["open_qubits"], [0])
+    ref = osv.simulate(text)
+    assert rel_l2(amps[0], ref) <= TOL
+    assert rel_l2(amps64[0], ref) <= TOL
+    assert abs(np.sum(np.abs(amps[0]) ** 2) - 1) < 1e-5
+
+
+@pytest.mark.parametrize("rows,cols,cycles,n_open,n_sliced,batched,seed", [
+    (3, 3, 6, 4, 0, 28, 1),      # fixed bits, no slicing
+    (4, 4, 8, 6, 3, 28, 2),      # slices carried as a batched mode
+    (4, 4, 8, 6, 3, 1, 3),       # slices looped (at most one batched leg)
+    (4, 5, 10, 8, 4, 2, 4),      # mixed looped / batched
+    (5, 4, 12, 10, 5, 28, 5),    # larger intermediates (stream + GEMM steps)
+])
+def test_sliced_batches_match_oracle(rqc, rows, cols, cycles, n_open, n_sliced, batched, seed):
+    text = circuit(rows, cols, cycles, seed=seed)
+    n = rows * cols
+    open_q = list(range(n - n_open, n))
+    fixed = synthetic.fixed_bits_batch(n, open_q, 1000 + seed, 3)
+    amps, amps64, info, _ = run_amplitudes(rqc, text, open_q, fixed, n_sliced_target=n_sliced,
+                                           max_log2_batched=batched)
+    assert info["n_sliced"] == n_sliced
+    ref = oracle_batches(text, fixed, open_q)
+    for b in range(len(fixed)):
+        assert rel_l2(amps[b], ref[b]) <= TOL, (b, rel_l2(amps[b], ref[b]))
+
+
+def test_single_amplitude_and_scalar_outputs(rqc):
+    """No open qubit: each batch is one amplitude."""
+    text = circuit(3, 3, 5, seed=6)
+    fixed = [0, 5, 511, 300]
+    amps, _, info, _ = run_amplitudes(rqc, text, [], fixed)
+    state = osv.simulate(text)
+    assert np.abs(amps[:, 0] - state[fixed]).max() <= TOL * np.abs(state).max() * 10
+
+
+def test_gemm_steps_are_exercised(rqc):
+    """A plan whose big steps run on the MFMA GEMM: parity and a non-zero GEMM share."""
+    text = circuit(4, 5, 14, seed=7)
+    open_q = list(range(8, 20))
+    fixed = synthetic.fixed_bits_batch(20, open_q, 2000, 2)
+    amps, _, info, _ = run_amplitudes(rqc, text, open_q, fixed, n_sliced_target=2, path_seed=3)
+    ref = oracle_batches(text, fixed, open_q)
+    for b in range(2):
+        assert rel_l2(amps[b], ref[b]) <= TOL
+    assert info["gemm_flop_share"] > 0
+
+
+def test_custom_slice_lists_sum_to_full(rqc):
+    """Sum over any split of the slice list equals the full result (slices are a
+    resolution of the identity, Sec. I)."""
+    import torch
+    text = circuit(4, 4, 8, seed=8)
+    open_q = list(range(8, 16))
+    c = rqc.load_circuit(text)
+    p = rqc.plan_create(c, open_q, n_sliced_target=4, max_log2_batched=1)
+    info = rqc.plan_info(p)
+    nb = info["n_batched"]
+    n_sl = info["n_slices"]
+    ids = list(range(n_sl))
+    legs = rqc.plan_sliced_legs(p)
+    assert len(legs) == 4
+    full = torch.empty((1, 256, 2), dtype=torch.float64, device="cuda")
+    part = torch.empty_like(full)
+    dummy = torch.empty((1, 256, 2), dtype=torch.float32, device="cuda")
+    rqc.contract_amplitudes(p, [0], dummy, full)
+    acc = torch.zeros_like(full)
+    # batched legs are the low slice-id bits for a greedy plan: split into whole groups
+    group = 1 << nb
+    halves = [ids[: n_sl // 2], ids[n_sl // 2:]]
+    for h in halves:
+        assert len(h) % group == 0
+        rqc.contract_amplitudes(p, [0], dummy, part, slice_ids=h)
+        acc += part
+    torch.cuda.synchronize()
+    assert torch.allclose(acc, full, atol=1e-6)
+    ref = oracle_batches(text, [0], open_q)[0]
+    got = full.cpu().numpy()[0]
+    assert rel_l2(got[:, 0] + 1j * got[:, 1], ref) <= TOL
+
+
+def test_sampler_batches_mode_bit_exact(rqc):
+    import torch
+    text = circuit(4, 4, 10, seed=9)
+    open_q = list(range(4, 16))
+    fixed = [0]
+    amps, _, _, _ = run_amplitudes(rqc, text, open_q, fixed)
+    A = amps.astype(np.complex64).reshape(-1, 64)
+    dev = torch.from_numpy(np.stack([A.real, A.imag], -1).astype(np.float32)).cuda()
+    out = torch.zeros(200, dtype=torch.int64, device="cuda")
+    n_out, st, code = rqc.rejection_sample(dev, fixed, open_q, 16, 200, out, alpha=2.0, F_norm=1.0, seed=7,
+                                           batch_index_base=5)
+    ref, rst = osamp.sample_batches(A, 6, 1 << 10, 2.0, 1.0, 7, 5, 200)
+    got = out.cpu().numpy()[:n_out].astype(np.uint64)
+    exp = []
+    for j, i in ref:
+        t = (j << 6) | i
+        bits = 0
+        for b, q in enumerate(open_q):
+            if (t >> b) & 1:
+                bits |= 1 << q
+        exp.append(bits)
+    assert n_out == len(exp) and [int(x) for x in got] == exp
+    assert st["accepted"] == rst["accepted"]
+    assert abs(st["eps_J"] - rst["eps_j"]) <= 1e-12
+
+
+@pytest.mark.parametrize("alpha", [2.0, 1.1])
+def test_sampler_pick_mode_bit_exact(rqc, alpha):
+    import torch
+    cfg = synthetic.CONFIGS["tiny"]
+    text = circuit(cfg["rows"], cfg["cols"], cfg["cycles"])
+    amps, _, _, _ = run_amplitudes(rqc, text, cfg["open_qubits"], [0])
+    a = amps[0].astype(np.complex64)
+    f_norm = float(osamp.probabilities(a).sum())
+    dev = torch.from_numpy(np.stack([a.real, a.imag], -1).astype(np.float32)).cuda()
+    out = torch.zeros(1000, dtype=torch.int64, device="cuda")
+    n_out, st, code = rqc.rejection_sample(dev, [0], cfg["open_qubits"], 12, 1000, out, alpha=alpha,
+                                           F_norm=f_norm, seed=7, pick_steps=4000)
+    ref, _ = osamp.sample_pick(a, 6, alpha, f_norm, 7, 1000, 4000)
+    exp = [(j << 6) | i for j, i in ref]
+    assert n_out == len(exp) == 1000
+    assert [int(x) for x in out.cpu().numpy()] == exp
+
+
+def test_sampler_short_status(rqc):
+    import torch
+    cfg = synthetic.CONFIGS["tiny"]
+    text = circuit(cfg["rows"], cfg["cols"], cfg["cycles"])
+    amps, _, _, _ = run_amplitudes(rqc, text, cfg["open_qubits"], [0])
+    a = amps[0].astype(np.complex64)
+    dev = torch.from_numpy(np.stack([a.real, a.imag], -1).astype(np.float32)).cuda()
+    out = torch.zeros(1000, dtype=torch.int64, device="cuda")
+    n_out, st, code = rqc.rejection_sample(dev, [0], cfg["open_qubits"], 12, 1000, out, pick_steps=100)
+    assert code == rqc.ESHORT and n_out < 1000
