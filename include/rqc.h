@@ -255,6 +255,28 @@ rqc_status rqc_rejection_sample(const void *amps, const uint64_t *fixed_bits, in
                                 uint64_t *out_samples, int64_t *n_out, rqc_sample_stats *stats,
                                 void *hip_stream);
 
+/*
+ * Kernel-level primitives (the contraction steps of Sec. I run on these; they
+ * are exported for direct use and for testing each kernel variant).
+ *
+ * Batched complex GEMM C[b] = A[b] B[b] (complex64, interleaved, device):
+ *   A element (m,k) of batch b at b*M*K + (a_kfast ? m*K + k : k*M + m),
+ *   B element (k,n) at b*K*N + (b_nfast ? k*N + n : n*K + k),
+ *   C element (m,n) at b*M*N + m*N + n.
+ * M and N must be powers of two >= 64, K a power of two >= 8.  precision is an
+ * rqc_precision; the split modes use 3 bf16/fp16 products per real product
+ * (fp16 with a per-operand power-of-two scale) and need K >= 16, otherwise
+ * the FP32 MFMA kernel runs.  Asynchronous on hip_stream.
+ */
+rqc_status rqc_kernel_cgemm(const void *A, const void *B, void *C, int64_t batch, int64_t M, int64_t N,
+                            int64_t K, int32_t a_kfast, int32_t b_nfast, int32_t precision, void *hip_stream);
+/*
+ * Bit permutation of a 2^r-element complex64 tensor (device):
+ * dst[sum_i bit_i(x) << perm[i]] = src[x]; perm (host) is a permutation of 0..r-1.
+ * Asynchronous on hip_stream.
+ */
+rqc_status rqc_kernel_permute(const void *src, void *dst, int32_t r, const int32_t *perm, void *hip_stream);
+
 /* Thread-local message for the last non-OK status (never NULL). */
 const char *rqc_last_error(void);
 /* Library version string. */

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librqc.so")
 
-SOURCES = ["circuit.cpp", "tree.cpp", "lower.cpp", "kernels.hip", "sampler.hip", "runtime.hip"]
+SOURCES = ["circuit.cpp", "tree.cpp", "lower.cpp", "plan.cpp", "kernels.hip", "sampler.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -4,6 +4,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -73,11 +74,28 @@ std::vector<Legs> tree_legs(const Tree &t, const std::vector<Legs> &leaf_legs, i
 double tree_log2_cost_sum(const Tree &t, const std::vector<Legs> &legs); // log2 sum 2^|A u B|
 
 Tree greedy_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
-                 uint64_t seed, double temperature);
+                 uint64_t seed, double temperature, double costmod = 1.0);
+
+// Re-optimise every subtree of up to `k` frontier tensors exactly (dynamic
+// programming over subsets), minimising flops plus written elements.
+Tree reconfigure_tree(const Tree &t, const std::vector<Legs> &leaf_legs, int n_vars,
+                      const std::vector<char> &kept, int k, int passes);
 
 std::vector<int> greedy_slice(const Tree &t, const std::vector<Legs> &legs, int n_vars,
                               const std::vector<char> &forbidden, int max_log2_tensor,
                               int n_target);
+
+// Randomised greedy trials (temperature and size weighting drawn per trial),
+// each followed by subtree reconfiguration and slicing; the trial with the
+// smallest total sliced cost wins.  Trials run on host threads.
+struct SearchResult {
+    Tree tree;
+    std::vector<int> sliced;
+    double log2cost = 0;
+};
+SearchResult search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
+                         const std::vector<char> &forbidden, const std::vector<int> *user_sliced,
+                         int max_log2_tensor, int n_target, int trials, uint64_t seed);
 
 // ------------------------------------------------------------------ light cones (Appendix B)
 struct LightCones {
@@ -142,6 +160,17 @@ struct Op {
     double flops, bytes;
 };
 
+// Leaf selection: copy a leaf's sub-tensor with its projected legs fixed.
+struct LeafSel {
+    int64_t src;          // offset of the full leaf in the leaf store (complex64 elements)
+    int64_t dst;          // offset of the projected leaf in the leaf buffer
+    int32_t n_free;       // legs kept
+    int32_t n_proj;       // legs fixed by projected values
+    uint8_t free_pos[4];  // full-layout bit of kept leg j
+    uint8_t proj_pos[4];  // full-layout bit of projected leg j
+    int16_t proj_idx[4];  // projected-variable index of projected leg j
+};
+
 struct Program {
     std::vector<SmallStep> small_steps;
     std::vector<SmallTree> small_trees;
@@ -159,5 +188,52 @@ struct Program {
     double flops = 0, bytes = 0, gemm_flops = 0;
     int max_log2 = 0;
 };
+
+// ------------------------------------------------------------------ planning
+// A network to plan: its leaves, the legs left open in the result (bit b of
+// the result index is open_vars[b]), legs fixed per batch (value = bit
+// fixed_bit[i] of the batch's mask) and legs that must not be sliced.
+struct NetSpec {
+    std::vector<Leaf> leaves;
+    int n_vars = 0;
+    std::vector<int> open_vars;
+    std::vector<int> fixed_vars, fixed_bit;
+    std::vector<char> forbidden;
+};
+
+NetSpec circuit_spec(const Network &net, const std::vector<int> &open_qubits);
+// Doubled network C_1 C_1^* of Fig. 1 for the partially sliced vertices S:
+// C_1 = union of the light cones of S; S legs are shared by both copies and
+// left open, the other outputs of C_1 are shared and summed.  Its result is
+// R[i] = ||psi_i||^2 (Sec. I.A), bit t of i = value of S[t].
+NetSpec doubled_spec(const Network &net, const std::vector<int> &S);
+void sort_leaf(Leaf &L);
+
+struct PlanCore {
+    rqc_plan_opts opts{};
+    NetSpec spec;
+    Tree tree;
+    std::vector<int> sliced, batched, looped;  // variable ids
+    std::vector<int> looped_bit, batched_bit;  // bit position of each in a slice id
+    bool user_legs = false;                    // sliced legs given by the caller (order kept)
+    std::vector<int> S;                        // partially sliced vertices (ascending)
+    std::vector<uint64_t> X;                   // kept partial indices, in selection order
+    std::vector<double> R;
+    double F = 1.0;
+    std::vector<uint64_t> groups;              // default slice groups: looped-leg values
+    Program prog;
+    std::vector<LeafSel> sel;
+    std::vector<cf> full;                      // leaf store
+    rqc_plan_info_t info{};
+};
+
+// Contraction tree and sliced legs (user path/legs or the randomised search).
+void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std::vector<int> *user_sliced);
+// Appendix B, Alg. 1: S by SlicedVertexSelect, R from `norms` (which contracts
+// the doubled network), X and F.
+void plan_partial(PlanCore &p, const Network &net,
+                  const std::function<std::vector<double>(const NetSpec &, const std::vector<int> &)> &norms);
+// Batched/looped split, projections, leaf selection, lowering and plan info.
+void plan_finish(PlanCore &p);
 
 } // namespace rqc

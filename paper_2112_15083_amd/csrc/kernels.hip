@@ -293,6 +293,228 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
             }
 }
 
+// ------------------------------------------------------------------ split-precision complex GEMM
+// Each FP32 operand value is written as x * s = hi + lo with hi, lo in bf16 or
+// fp16 (s = 1 for bf16; a per-tensor power of two for fp16 that brings the
+// tensor's largest magnitude into [2^14, 2^15)).  A real product is taken as
+// hi*hi' + hi*lo' + lo*hi' (lo*lo' dropped), accumulated in FP32 on MFMA.  The
+// complex product uses the interleaved real view A'[m][2k+c] = (re, im) and
+//   B'_re[2k][n] = re, B'_re[2k+1][n] = -im;  B'_im[2k][n] = im, B'_im[2k+1][n] = re,
+// so C_re = A' B'_re and C_im = A' B'_im are plain real GEMMs over 2K.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+template <bool F16>
+struct SplitT {
+    using E = __bf16;
+    using V8 = bf16x8;
+    static __device__ __forceinline__ floatx16 mma(V8 a, V8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct SplitT<true> {
+    using E = _Float16;
+    using V8 = half8;
+    static __device__ __forceinline__ floatx16 mma(V8 a, V8 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// scale exponent for a tensor whose largest magnitude is amax (fp16 mode)
+__device__ __forceinline__ int split_exp(float amax) {
+    if (!(amax > 0.f) || !isfinite(amax)) return 0;
+    int e = ilogbf(amax);
+    int s = 14 - e;
+    return s < -120 ? -120 : (s > 120 ? 120 : s);
+}
+
+template <int BM, int BN, int A_KFAST, int B_NFAST, bool F16>
+__global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned *__restrict__ amax) {
+    using E = typename SplitT<F16>::E;
+    using V8 = typename SplitT<F16>::V8;
+    constexpr int BK = 16, BK2 = 32, LD = BK2 + 8;
+    constexpr int WM = BM / 64, WN = BN / 64;
+    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+    __shared__ __attribute__((aligned(16))) E Ah[BM][LD];
+    __shared__ __attribute__((aligned(16))) E Al[BM][LD];
+    __shared__ __attribute__((aligned(16))) E Brh[BN][LD];
+    __shared__ __attribute__((aligned(16))) E Brl[BN][LD];
+    __shared__ __attribute__((aligned(16))) E Bih[BN][LD];
+    __shared__ __attribute__((aligned(16))) E Bil[BN][LD];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t ntn = g.N / BN, ntm = g.M / BM;
+    const int64_t bid = blockIdx.x;
+    const int64_t bz = bid / (ntn * ntm);
+    const int64_t m0 = ((bid / ntn) % ntm) * BM, n0 = (bid % ntn) * BN;
+    const float2 *A = g.A + bz * g.sa;
+    const float2 *B = g.B + bz * g.sb;
+    float2 *C = g.C + bz * g.sc;
+    const int64_t M = g.M, N = g.N, K = g.K;
+    int ea = 0, eb = 0;
+    if (F16) {
+        ea = split_exp(__uint_as_float(amax[0]));
+        eb = split_exp(__uint_as_float(amax[1]));
+    }
+    const float sa = ldexpf(1.f, ea), sb = ldexpf(1.f, eb);
+
+    int a_r, a_c, b_r, b_c;
+    if (A_KFAST) { a_r = tid / (BK / EA); a_c = (tid % (BK / EA)) * EA; }
+    else { a_r = tid / (BM / EA); a_c = (tid % (BM / EA)) * EA; }
+    if (B_NFAST) { b_r = tid / (BN / EB); b_c = (tid % (BN / EB)) * EB; }
+    else { b_r = tid / (BK / EB); b_c = (tid % (BK / EB)) * EB; }
+
+    float2 ra[EA], rb[EB];
+    auto gload = [&](int64_t k0) {
+        const float2 *pa = A_KFAST ? A + (m0 + a_r) * K + k0 + a_c : A + (k0 + a_r) * M + m0 + a_c;
+        const float2 *pb = B_NFAST ? B + (k0 + b_r) * N + n0 + b_c : B + (n0 + b_r) * K + k0 + b_c;
+#pragma unroll
+        for (int e = 0; e < EA; e += 2) {
+            float4 v = *reinterpret_cast<const float4 *>(pa + e);
+            ra[e] = make_float2(v.x, v.y);
+            ra[e + 1] = make_float2(v.z, v.w);
+        }
+#pragma unroll
+        for (int e = 0; e < EB; e += 2) {
+            float4 v = *reinterpret_cast<const float4 *>(pb + e);
+            rb[e] = make_float2(v.x, v.y);
+            rb[e + 1] = make_float2(v.z, v.w);
+        }
+    };
+    auto split = [&](float x, E &hi, E &lo) {
+        hi = (E)x;
+        lo = (E)(x - (float)hi);
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int e = 0; e < EA; e++) {
+            const int kk = A_KFAST ? a_c + e : a_r, mm = A_KFAST ? a_r : a_c + e;
+            E h0, l0, h1, l1;
+            split(ra[e].x * sa, h0, l0);
+            split(ra[e].y * sa, h1, l1);
+            Ah[mm][2 * kk] = h0;
+            Ah[mm][2 * kk + 1] = h1;
+            Al[mm][2 * kk] = l0;
+            Al[mm][2 * kk + 1] = l1;
+        }
+#pragma unroll
+        for (int e = 0; e < EB; e++) {
+            const int kk = B_NFAST ? b_r : b_c + e, nn = B_NFAST ? b_c + e : b_r;
+            E hr, lr, hi_, li;
+            split(rb[e].x * sb, hr, lr);
+            split(rb[e].y * sb, hi_, li);
+            Brh[nn][2 * kk] = hr;
+            Brh[nn][2 * kk + 1] = -hi_;
+            Brl[nn][2 * kk] = lr;
+            Brl[nn][2 * kk + 1] = -li;
+            Bih[nn][2 * kk] = hi_;
+            Bih[nn][2 * kk + 1] = hr;
+            Bil[nn][2 * kk] = li;
+            Bil[nn][2 * kk + 1] = lr;
+        }
+    };
+
+    floatx16 cre[WM][WN], cim[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; i++)
+#pragma unroll
+        for (int j = 0; j < WN; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) cre[i][j][v] = 0.f, cim[i][j][v] = 0.f;
+
+    const int nk = (int)(K / BK);
+    gload(0);
+    for (int kt = 0; kt < nk; kt++) {
+        sstore();
+        __syncthreads();
+        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK2; ks += 16) {
+            const int ko = ks + 8 * (lane >> 5);
+            V8 ah[WM], al[WM], brh[WN], brl[WN], bih[WN], bil[WN];
+#pragma unroll
+            for (int i = 0; i < WM; i++) {
+                const int mm = wm * (BM / 2) + i * 32 + (lane & 31);
+                ah[i] = *reinterpret_cast<const V8 *>(&Ah[mm][ko]);
+                al[i] = *reinterpret_cast<const V8 *>(&Al[mm][ko]);
+            }
+#pragma unroll
+            for (int j = 0; j < WN; j++) {
+                const int nn = wn * (BN / 2) + j * 32 + (lane & 31);
+                brh[j] = *reinterpret_cast<const V8 *>(&Brh[nn][ko]);
+                brl[j] = *reinterpret_cast<const V8 *>(&Brl[nn][ko]);
+                bih[j] = *reinterpret_cast<const V8 *>(&Bih[nn][ko]);
+                bil[j] = *reinterpret_cast<const V8 *>(&Bil[nn][ko]);
+            }
+#pragma unroll
+            for (int i = 0; i < WM; i++)
+#pragma unroll
+                for (int j = 0; j < WN; j++) {
+                    cre[i][j] = SplitT<F16>::mma(ah[i], brh[j], cre[i][j]);
+                    cre[i][j] = SplitT<F16>::mma(ah[i], brl[j], cre[i][j]);
+                    cre[i][j] = SplitT<F16>::mma(al[i], brh[j], cre[i][j]);
+                    cim[i][j] = SplitT<F16>::mma(ah[i], bih[j], cim[i][j]);
+                    cim[i][j] = SplitT<F16>::mma(ah[i], bil[j], cim[i][j]);
+                    cim[i][j] = SplitT<F16>::mma(al[i], bih[j], cim[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < WM; i++)
+#pragma unroll
+        for (int j = 0; j < WN; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int64_t m = m0 + wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int64_t n = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
+                float re = cre[i][j][v], im = cim[i][j][v];
+                if (F16) {
+                    re = ldexpf(ldexpf(re, -ea), -eb);
+                    im = ldexpf(ldexpf(im, -ea), -eb);
+                }
+                C[m * N + n] = make_float2(re, im);
+            }
+}
+
+__global__ void __launch_bounds__(256) k_absmax(const float *__restrict__ x, int64_t n, unsigned *__restrict__ out) {
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(x[i]));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+template <int BM, int BN, bool F16>
+static void split_dispatch(const GemmArgs &g, const unsigned *amax, hipStream_t s) {
+    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch));
+    if (g.a_kfast && g.b_nfast) hipLaunchKernelGGL((k_cgemm_split<BM, BN, 1, 1, F16>), grid, dim3(256), 0, s, g, amax);
+    else if (g.a_kfast) hipLaunchKernelGGL((k_cgemm_split<BM, BN, 1, 0, F16>), grid, dim3(256), 0, s, g, amax);
+    else if (g.b_nfast) hipLaunchKernelGGL((k_cgemm_split<BM, BN, 0, 1, F16>), grid, dim3(256), 0, s, g, amax);
+    else hipLaunchKernelGGL((k_cgemm_split<BM, BN, 0, 0, F16>), grid, dim3(256), 0, s, g, amax);
+}
+
+template <bool F16>
+static void split_gemm(const GemmArgs &g, unsigned *amax, hipStream_t s) {
+    if (F16) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, amax, 2);
+        const int64_t na = 2 * g.batch * g.M * g.K, nb = 2 * g.batch * g.K * g.N;
+        auto blocks = [](int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 2048); };
+        hipLaunchKernelGGL(k_absmax, dim3(blocks(na)), dim3(256), 0, s, (const float *)g.A, na, amax);
+        hipLaunchKernelGGL(k_absmax, dim3(blocks(nb)), dim3(256), 0, s, (const float *)g.B, nb, amax + 1);
+    }
+    if (g.M >= 128 && g.N >= 128) split_dispatch<128, 128, F16>(g, amax, s);
+    else if (g.M >= 128) split_dispatch<128, 64, F16>(g, amax, s);
+    else if (g.N >= 128) split_dispatch<64, 128, F16>(g, amax, s);
+    else split_dispatch<64, 64, F16>(g, amax, s);
+}
+
 template <int BM, int BN>
 static void gemm_dispatch(const GemmArgs &g, hipStream_t s) {
     dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch));
@@ -302,8 +524,10 @@ static void gemm_dispatch(const GemmArgs &g, hipStream_t s) {
     else hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 0>), grid, dim3(256), 0, s, g);
 }
 
-void launch_gemm(const GemmArgs &g, int precision, hipStream_t s) {
-    (void)precision;
+void launch_gemm(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s) {
+    // the split kernels stage 16 complex k per step; shorter contractions stay FP32
+    if (precision == RQC_BF16X3 && g.K >= 16) return split_gemm<false>(g, amax, s);
+    if (precision == RQC_FP16X3 && g.K >= 16) return split_gemm<true>(g, amax, s);
     if (g.M >= 128 && g.N >= 128) gemm_dispatch<128, 128>(g, s);
     else if (g.M >= 128) gemm_dispatch<128, 64>(g, s);
     else if (g.N >= 128) gemm_dispatch<64, 128>(g, s);

@@ -13,17 +13,6 @@ struct ProjVals {
     uint64_t w[4];
 };
 
-// Leaf selection: copy a leaf's sub-tensor with its projected legs fixed.
-struct LeafSel {
-    int64_t src;        // offset of the full leaf in the leaf store (complex64 elements)
-    int64_t dst;        // offset of the projected leaf in the leaf buffer
-    int32_t n_free;     // legs kept
-    int32_t n_proj;     // legs fixed by projected values
-    uint8_t free_pos[4];  // full-layout bit of kept leg j
-    uint8_t proj_pos[4];  // full-layout bit of projected leg j
-    int16_t proj_idx[4];  // projected-variable index of projected leg j
-};
-
 // Tiled bit permutation: dst[P(x)] = src[x].
 struct PermDesc {
     BitMap tile_src, tile_dst; // tile index -> source / destination base offset
@@ -49,7 +38,8 @@ void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int 
                         const float2 *leafbuf, float2 *arena, hipStream_t s);
 void launch_stream(const StreamOp &op, const float2 *a, const float2 *b, float2 *c, hipStream_t s);
 void launch_permute(const PermDesc &d, const float2 *src, float2 *dst, hipStream_t s);
-void launch_gemm(const GemmArgs &g, int precision, hipStream_t s);
+// precision: rqc_precision; amax: two device words of scratch (fp16 scaling)
+void launch_gemm(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s);
 void launch_accumulate(const float2 *root, const BitMap &open_map, const BitMap &slice_map, int n_open,
                        int n_batched, double2 *acc, hipStream_t s);
 void launch_zero(double2 *acc, int64_t n, hipStream_t s);

@@ -1,13 +1,15 @@
-// C-ABI of librqc: circuit handles, planning, the slice-group executor and the
-// sampler entry point.
+// C-ABI of librqc: circuit handles, plan creation and upload, the slice-group
+// executor, the sampler entry point and the kernel-level primitives.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
-#include <mutex>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 
@@ -24,10 +26,6 @@ void fail(rqc_status code, const std::string &msg) { throw Error{code, msg}; }
         hipError_t e_ = (x);                                                                        \
         if (e_ != hipSuccess) rqc::fail(RQC_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
-
-// Planning helpers declared in lower.cpp
-Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
-                   std::vector<int> &root_layout);
 
 static void check_device() {
     int dev = 0;
@@ -53,25 +51,9 @@ struct PendingEvent {
     double flops, bytes;
 };
 
-struct rqc_plan {
+struct rqc_plan : PlanCore {
     int device = 0;
-    rqc_plan_opts opts{};
-    Network net;
-    Tree tree;
-    std::vector<int> open_qubits;
-    std::vector<int> sliced, batched, looped; // variable ids
-    std::vector<int> looped_bit, batched_bit; // bit position of each in a slice id
-    // partial slicing
-    std::vector<int> S;
-    std::vector<int> S_bit;                   // bit position of S members in a slice id
-    std::vector<uint64_t> X;
-    std::vector<double> R;
-    double F = 1.0;
-    // projected variables: fixed output qubits first, then looped legs
-    std::vector<int> fixed_qubit;
-    Program prog;
     std::vector<PermDesc> perm_desc;
-    rqc_plan_info_t info{};
     // device memory
     std::vector<std::pair<void *, size_t>> owned;
     float2 *d_full = nullptr, *d_leafbuf = nullptr, *d_arena = nullptr;
@@ -79,11 +61,13 @@ struct rqc_plan {
     SmallStep *d_steps = nullptr;
     SmallTree *d_trees = nullptr;
     double2 *d_acc = nullptr;
-    int n_leaves = 0;
+    unsigned *d_amax = nullptr; // operand maxima for the fp16 split scaling
     // profiling
     rqc_profile_t prof{};
     std::vector<PendingEvent> pending;
     std::vector<hipEvent_t> pool;
+
+    ~rqc_plan() { release(); }
 
     void *dalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
@@ -136,6 +120,36 @@ struct rqc_plan {
         }
         pending.clear();
     }
+    void upload() {
+        const Program &pg = prog;
+        for (auto &op : pg.permutes) perm_desc.push_back(make_perm_desc(op.r, op.perm));
+        if (opts.dry_run) return;
+        try {
+            std::vector<float2> f(full.size());
+            for (size_t i = 0; i < full.size(); i++) f[i] = make_float2(full[i].real(), full[i].imag());
+            d_full = (float2 *)dalloc(f.size() * sizeof(float2));
+            d_sel = (LeafSel *)dalloc(sel.size() * sizeof(LeafSel));
+            d_leafbuf = (float2 *)dalloc((size_t)pg.leafbuf_elems * sizeof(float2));
+            d_arena = (float2 *)dalloc((size_t)std::max<int64_t>(pg.arena_elems, 64) * sizeof(float2));
+            d_steps = (SmallStep *)dalloc(std::max<size_t>(1, pg.small_steps.size()) * sizeof(SmallStep));
+            d_trees = (SmallTree *)dalloc(std::max<size_t>(1, pg.small_trees.size()) * sizeof(SmallTree));
+            d_acc = (double2 *)dalloc(((size_t)1 << spec.open_vars.size()) * sizeof(double2));
+            d_amax = (unsigned *)dalloc(256);
+            HIP_OK(hipMemcpy(d_full, f.data(), f.size() * sizeof(float2), hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d_sel, sel.data(), sel.size() * sizeof(LeafSel), hipMemcpyHostToDevice));
+            if (!pg.small_steps.empty())
+                HIP_OK(hipMemcpy(d_steps, pg.small_steps.data(), pg.small_steps.size() * sizeof(SmallStep),
+                                 hipMemcpyHostToDevice));
+            if (!pg.small_trees.empty())
+                HIP_OK(hipMemcpy(d_trees, pg.small_trees.data(), pg.small_trees.size() * sizeof(SmallTree),
+                                 hipMemcpyHostToDevice));
+        } catch (...) {
+            release();
+            throw;
+        }
+        info.workspace_bytes = 0;
+        for (auto &o : owned) info.workspace_bytes += (int64_t)o.second;
+    }
 };
 
 namespace {
@@ -178,14 +192,154 @@ rqc_status guard(F &&f) {
     }
 }
 
-std::vector<Legs> leaf_leg_sets(const Network &net) {
-    std::vector<Legs> out;
-    for (auto &L : net.leaves) {
-        Legs l(L.legs);
-        std::sort(l.begin(), l.end());
-        out.push_back(l);
+void dump_plan(const rqc_plan &p) {
+    const Program &pg = p.prog;
+    std::fprintf(stderr, "plan: %zu fused subtrees (%zu steps, %d LDS elems), %zu ops, arena %lld elems, %zu groups\n",
+                 pg.small_trees.size(), pg.small_steps.size(), pg.small_lds_elems, pg.ops.size(),
+                 (long long)pg.arena_elems, p.groups.size());
+    for (const Op &op : pg.ops) {
+        if (op.kind == OP_STREAM) {
+            const StreamOp &so = pg.streams[op.index];
+            std::fprintf(stderr, "  stream rc=%d kc=%d flops=%.3g bytes=%.3g\n", so.rc, so.kc, op.flops, op.bytes);
+        } else if (op.kind == OP_GEMM) {
+            const GemmOp &g = pg.gemms[op.index];
+            std::fprintf(stderr, "  gemm b=%lld M=%lld N=%lld K=%lld ak=%d bn=%d flops=%.3g\n", (long long)g.batch,
+                         (long long)g.M, (long long)g.N, (long long)g.K, g.a_kfast, g.b_nfast, op.flops);
+        } else if (op.kind == OP_PERMUTE) {
+            std::fprintf(stderr, "  permute r=%d bytes=%.3g\n", pg.permutes[op.index].r, op.bytes);
+        } else {
+            std::fprintf(stderr, "  fused subtrees: %zu\n", pg.small_trees.size());
+        }
     }
-    return out;
+}
+
+// Run the plan's program for every (batch, slice group) pair.
+void execute(rqc_plan *p, const std::vector<uint64_t> &groups, const uint64_t *fixed_bits, int64_t n_batches,
+             void *out_amps, void *out_f64, hipStream_t s) {
+    const Program &pg = p->prog;
+    const int n_open = (int)p->spec.open_vars.size();
+    const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
+    const int64_t nout = (int64_t)1 << n_open;
+    const double scale = 1.0 / std::sqrt(p->F);
+    const int nfix = (int)p->spec.fixed_vars.size();
+    auto ptr = [&](const Buf &b) -> float2 * { return (b.kind == 0 ? p->d_arena : p->d_leafbuf) + b.off; };
+    for (int64_t bi = 0; bi < n_batches; bi++) {
+        {
+            Timer t(p, s, RQC_K_ACCUM, 0, 16.0 * nout);
+            launch_zero(p->d_acc, nout, s);
+        }
+        for (uint64_t g : groups) {
+            ProjVals vals{};
+            for (int i = 0; i < nfix; i++)
+                if ((fixed_bits[bi] >> p->spec.fixed_bit[i]) & 1) vals.w[i >> 6] |= 1ull << (i & 63);
+            for (int u = 0; u < nl; u++)
+                if ((g >> u) & 1) {
+                    const int idx = nfix + u;
+                    vals.w[idx >> 6] |= 1ull << (idx & 63);
+                }
+            {
+                Timer t(p, s, RQC_K_LEAF, 0, 16.0 * (double)pg.leafbuf_elems);
+                launch_leaf_select(p->d_full, p->d_leafbuf, p->d_sel, (int)p->sel.size(), vals, s);
+            }
+            for (const Op &op : pg.ops) {
+                switch (op.kind) {
+                case OP_SMALL: {
+                    Timer t(p, s, RQC_K_SMALL, op.flops, op.bytes);
+                    launch_small_trees(p->d_steps, p->d_trees, (int)pg.small_trees.size(), pg.small_lds_elems,
+                                       p->d_leafbuf, p->d_arena, s);
+                    break;
+                }
+                case OP_STREAM: {
+                    const StreamOp &so = pg.streams[op.index];
+                    Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
+                    launch_stream(so, ptr(so.a), ptr(so.b), ptr(so.c), s);
+                    break;
+                }
+                case OP_PERMUTE: {
+                    const PermuteOp &po = pg.permutes[op.index];
+                    Timer t(p, s, RQC_K_PERMUTE, op.flops, op.bytes);
+                    launch_permute(p->perm_desc[op.index], ptr(po.src), ptr(po.dst), s);
+                    break;
+                }
+                case OP_GEMM: {
+                    const GemmOp &go = pg.gemms[op.index];
+                    GemmArgs ga;
+                    ga.A = ptr(go.a);
+                    ga.B = ptr(go.b);
+                    ga.C = ptr(go.c);
+                    ga.batch = go.batch;
+                    ga.M = go.M;
+                    ga.N = go.N;
+                    ga.K = go.K;
+                    ga.sa = go.sa;
+                    ga.sb = go.sb;
+                    ga.sc = go.sc;
+                    ga.a_kfast = go.a_kfast;
+                    ga.b_nfast = go.b_nfast;
+                    Timer t(p, s, RQC_K_GEMM, op.flops, op.bytes);
+                    launch_gemm(ga, p->opts.precision, p->d_amax, s);
+                    break;
+                }
+                }
+            }
+            {
+                Timer t(p, s, RQC_K_ACCUM, 0, 8.0 * (double)(nout << nb) + 32.0 * nout);
+                launch_accumulate(ptr(pg.root), pg.root_open, pg.root_slice, n_open, nb, p->d_acc, s);
+            }
+        }
+        {
+            Timer t(p, s, RQC_K_FINAL, 0, 16.0 * nout + 8.0 * nout);
+            launch_finalize(p->d_acc, nout, scale, (float2 *)out_amps + bi * nout,
+                            out_f64 ? (double2 *)out_f64 + bi * nout : nullptr, s);
+        }
+    }
+    HIP_OK(hipGetLastError());
+    if (p->opts.profile && p->pending.size() > 8192) p->flush_profile();
+}
+
+// R[i] = ||psi_i||^2 by contracting the doubled network on the GPU (Fig. 1).
+std::vector<double> gpu_norms(const rqc_plan_opts &outer, const NetSpec &spec, const std::vector<int> &S) {
+    auto P = std::make_unique<rqc_plan>();
+    rqc_plan &q = *P;
+    q.opts = rqc_plan_opts{};
+    q.opts.max_log2_tensor = 28;
+    q.opts.n_sliced_target = -1;
+    q.opts.max_log2_batched = 28;
+    q.opts.path_trials = 32;
+    q.opts.path_seed = outer.path_seed;
+    q.opts.alloc = outer.alloc;
+    q.opts.free = outer.free;
+    q.opts.alloc_ctx = outer.alloc_ctx;
+    q.spec = spec;
+    q.info.n_qubits = 0;
+    plan_tree(q, nullptr, 0, nullptr);
+    plan_finish(q);
+    HIP_OK(hipGetDevice(&q.device));
+    q.upload();
+    const size_t n = (size_t)1 << S.size();
+    float2 *amps = nullptr;
+    double2 *r64 = nullptr;
+    HIP_OK(hipMalloc(&amps, n * sizeof(float2)));
+    hipError_t e = hipMalloc(&r64, n * sizeof(double2));
+    if (e != hipSuccess) {
+        (void)hipFree(amps);
+        fail(RQC_ENOMEM, "norm tensor allocation failed");
+    }
+    std::vector<double2> host(n);
+    try {
+        uint64_t zero = 0;
+        execute(&q, q.groups, &zero, 1, amps, r64, nullptr);
+        HIP_OK(hipMemcpy(host.data(), r64, n * sizeof(double2), hipMemcpyDeviceToHost));
+    } catch (...) {
+        (void)hipFree(amps);
+        (void)hipFree(r64);
+        throw;
+    }
+    (void)hipFree(amps);
+    (void)hipFree(r64);
+    std::vector<double> R(n);
+    for (size_t i = 0; i < n; i++) R[i] = host[i].x;
+    return R;
 }
 
 } // namespace
@@ -193,20 +347,15 @@ std::vector<Legs> leaf_leg_sets(const Network &net) {
 extern "C" {
 
 const char *rqc_last_error(void) { return g_err.c_str(); }
-const char *rqc_version(void) { return "librqc 0.1 (gfx950)"; }
+const char *rqc_version(void) { return "librqc 0.2 (gfx950)"; }
 
 rqc_status rqc_load_circuit(const char *text, size_t len, rqc_circuit **out) {
     return guard([&] {
         if (!text || !out) fail(RQC_EINVAL, "null argument");
-        auto *c = new rqc_circuit;
-        try {
-            c->c = parse_circuit(text, len);
-            c->net = build_network(c->c);
-        } catch (...) {
-            delete c;
-            throw;
-        }
-        *out = c;
+        auto c = std::make_unique<rqc_circuit>();
+        c->c = parse_circuit(text, len);
+        c->net = build_network(c->c);
+        *out = c.release();
     });
 }
 
@@ -228,262 +377,34 @@ rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_
         if (!c || !out) fail(RQC_EINVAL, "null argument");
         if (n_open < 0 || n_open > c->c.n || (n_open > 0 && !open_qubits)) fail(RQC_EINVAL, "bad open qubits");
         if (n_open > 30) fail(RQC_EINVAL, "at most 30 open qubits");
+        if (n_sliced < 0 || n_path_pairs < 0) fail(RQC_EINVAL, "negative count");
         auto t0 = std::chrono::steady_clock::now();
         auto P = std::make_unique<rqc_plan>();
         rqc_plan &p = *P;
         if (opts) p.opts = *opts;
         if (p.opts.max_log2_batched <= 0) p.opts.max_log2_batched = 28;
         if (p.opts.precision < 0 || p.opts.precision > 2) fail(RQC_EINVAL, "unknown precision");
+        const double f = p.opts.target_fidelity;
+        const bool partial = f > 0 && f < 1;
+        if (partial && p.opts.dry_run) fail(RQC_EINVAL, "partial slicing computes its norms on the GPU");
         if (!p.opts.dry_run) {
             check_device();
             HIP_OK(hipGetDevice(&p.device));
         }
-        p.net = c->net;
-        const Network &net = p.net;
-        const int n = net.n_qubits, nv = net.n_vars;
-        std::vector<char> is_open(n, 0);
-        for (int b = 0; b < n_open; b++) {
-            int q = open_qubits[b];
-            if (q < 0 || q >= n || is_open[q]) fail(RQC_EINVAL, "open qubits must be distinct and in range");
-            is_open[q] = 1;
-            p.open_qubits.push_back(q);
+        std::vector<int> oq(open_qubits, open_qubits + n_open);
+        p.spec = circuit_spec(c->net, oq);
+        p.info.n_qubits = c->c.n;
+        std::vector<int> user;
+        if (sliced_legs) user.assign(sliced_legs, sliced_legs + n_sliced);
+        plan_tree(p, path, n_path_pairs, sliced_legs ? &user : nullptr);
+        if (partial) {
+            rqc_plan_opts o = p.opts;
+            plan_partial(p, c->net, [&](const NetSpec &ds, const std::vector<int> &S) { return gpu_norms(o, ds, S); });
         }
-        std::vector<char> kept(nv, 0), fixed_out(nv, 0), forbidden(nv, 0);
-        for (int v = 0; v < n && v < nv; v++) forbidden[v] = 1;
-        for (int q = 0; q < n; q++) {
-            forbidden[net.out_var[q]] = 1;
-            if (is_open[q]) kept[net.out_var[q]] = 1;
-            else fixed_out[net.out_var[q]] = 1;
-        }
-        std::vector<Legs> leaf_legs = leaf_leg_sets(net);
-        std::vector<Legs> path_legs(leaf_legs.size());
-        for (size_t i = 0; i < leaf_legs.size(); i++)
-            for (int v : leaf_legs[i])
-                if (!fixed_out[v]) path_legs[i].push_back(v);
-        // -------- contraction tree and sliced legs
-        std::vector<char> none(nv, 0);
-        std::vector<int> user_sliced;
-        if (sliced_legs) {
-            std::vector<char> seen(nv, 0);
-            for (int i = 0; i < n_sliced; i++) {
-                int v = sliced_legs[i];
-                if (v < 0 || v >= nv || forbidden[v] || seen[v])
-                    fail(RQC_EINVAL, "sliced leg " + std::to_string(v) + " is not an internal variable");
-                seen[v] = 1;
-                user_sliced.push_back(v);
-            }
-        }
-        if (path) {
-            Tree t;
-            t.n_leaves = (int)leaf_legs.size();
-            std::vector<char> used(t.n_leaves + n_path_pairs, 0);
-            for (int s = 0; s < n_path_pairs; s++) {
-                int a = path[2 * s], b = path[2 * s + 1];
-                int lim = t.n_leaves + s;
-                if (a < 0 || b < 0 || a >= lim || b >= lim || a == b || used[a] || used[b])
-                    fail(RQC_EINVAL, "path pair " + std::to_string(s) + " is not a valid SSA pair");
-                used[a] = used[b] = 1;
-                t.steps.push_back({a, b});
-            }
-            if (n_path_pairs != t.n_leaves - 1) fail(RQC_EINVAL, "path must contract all tensors into one");
-            p.tree = t;
-            if (!sliced_legs) {
-                auto legs = tree_legs(t, path_legs, nv, fixed_out, kept);
-                p.sliced = greedy_slice(t, legs, nv, forbidden, p.opts.max_log2_tensor, p.opts.n_sliced_target);
-            } else {
-                p.sliced = user_sliced;
-            }
-        } else {
-            int trials = p.opts.path_trials > 0 ? p.opts.path_trials : 16;
-            double best = 1e300;
-            for (int tr = 0; tr < trials; tr++) {
-                double temp = tr == 0 ? 0.0 : 0.1 + 0.9 * (double)(tr % 8) / 8.0;
-                Tree t = greedy_tree(path_legs, nv, kept, p.opts.path_seed * 1000003ull + (uint64_t)tr, temp);
-                auto legs = tree_legs(t, path_legs, nv, fixed_out, kept);
-                std::vector<int> sl = sliced_legs ? user_sliced
-                                                  : greedy_slice(t, legs, nv, forbidden, p.opts.max_log2_tensor,
-                                                                 p.opts.n_sliced_target);
-                std::vector<char> rem(fixed_out);
-                for (int v : sl) rem[v] = 1;
-                auto legs2 = tree_legs(t, path_legs, nv, rem, kept);
-                double cost = tree_log2_cost_sum(t, legs2) + (double)sl.size();
-                if (cost < best - 1e-9) {
-                    best = cost;
-                    p.tree = t;
-                    p.sliced = sl;
-                }
-            }
-        }
-        // unsliced cost, for reporting
-        {
-            auto legs0 = tree_legs(p.tree, path_legs, nv, fixed_out, kept);
-            p.info.flops_unsliced = 8.0 * std::exp2(tree_log2_cost_sum(p.tree, legs0));
-        }
-        if (p.sliced.size() > 62) fail(RQC_EPLAN, "more than 62 sliced legs");
-        // -------- partial slicing (Alg. 1 and 2)
-        const double f = p.opts.target_fidelity;
-        const bool partial = f > 0 && f < 1;
-        if (partial) fail(RQC_EINVAL, "partial slicing is not available in this build");
-        // -------- batched legs: greedy, within the memory budget
-        std::vector<int> cand;
-        for (int v : p.sliced)
-            if (std::find(p.S.begin(), p.S.end(), v) == p.S.end()) cand.push_back(v);
-        std::vector<int> B;
-        for (;;) {
-            int bestv = -1;
-            double best_key = 1e300;
-            for (int v : cand) {
-                if (std::find(B.begin(), B.end(), v) != B.end()) continue;
-                std::vector<char> rem(fixed_out), kp(kept);
-                for (int u : p.sliced) rem[u] = 1;
-                for (int u : B) rem[u] = 0, kp[u] = 1;
-                rem[v] = 0;
-                kp[v] = 1;
-                auto lg = tree_legs(p.tree, path_legs, nv, rem, kp);
-                size_t mx = 0;
-                double tot = 0;
-                for (auto &l : lg) mx = std::max(mx, l.size()), tot += std::exp2((double)l.size());
-                if ((int)mx > p.opts.max_log2_batched) continue;
-                double key = (double)mx * 1e30 + tot;
-                if (key < best_key) best_key = key, bestv = v;
-            }
-            if (bestv < 0) break;
-            B.push_back(bestv);
-        }
-        // slice-id bit order: greedy-sliced legs are reordered batched-first so the
-        // fixed FP64 summation order is ascending slice id; user legs keep their order
-        if (!sliced_legs) {
-            std::vector<int> ord;
-            for (int v : p.sliced)
-                if (std::find(B.begin(), B.end(), v) != B.end()) ord.push_back(v);
-            for (int v : p.sliced)
-                if (std::find(B.begin(), B.end(), v) == B.end()) ord.push_back(v);
-            p.sliced = ord;
-        }
-        for (size_t t = 0; t < p.sliced.size(); t++) {
-            int v = p.sliced[t];
-            if (std::find(B.begin(), B.end(), v) != B.end()) {
-                p.batched.push_back(v);
-                p.batched_bit.push_back((int)t);
-            } else {
-                p.looped.push_back(v);
-                p.looped_bit.push_back((int)t);
-            }
-        }
-        // -------- final leg sets
-        std::vector<char> rem(fixed_out), kp(kept);
-        for (int v : p.looped) rem[v] = 1;
-        for (int v : p.batched) kp[v] = 1;
-        auto legs = tree_legs(p.tree, path_legs, nv, rem, kp);
-        // projected variables
-        std::vector<int> pidx(nv, -1);
-        int np = 0;
-        for (int q = 0; q < n; q++)
-            if (!is_open[q]) {
-                pidx[net.out_var[q]] = np++;
-                p.fixed_qubit.push_back(q);
-            }
-        for (int v : p.looped) pidx[v] = np++;
-        if (np > 256) fail(RQC_EPLAN, "more than 256 projected variables");
-        // leaf buffer layout and selection descriptors
-        p.n_leaves = (int)net.leaves.size();
-        std::vector<int> leaf_off(p.n_leaves);
-        std::vector<LeafSel> sel(p.n_leaves);
-        int64_t full_off = 0, buf_off = 0;
-        for (int i = 0; i < p.n_leaves; i++) {
-            const Leaf &L = net.leaves[i];
-            LeafSel d{};
-            d.src = full_off;
-            d.dst = buf_off;
-            leaf_off[i] = (int)buf_off;
-            for (size_t j = 0; j < L.legs.size(); j++) {
-                int v = L.legs[j];
-                if (std::binary_search(legs[i].begin(), legs[i].end(), v)) d.free_pos[d.n_free++] = (uint8_t)j;
-                else if (pidx[v] >= 0) {
-                    d.proj_pos[d.n_proj] = (uint8_t)j;
-                    d.proj_idx[d.n_proj++] = (int16_t)pidx[v];
-                } else
-                    fail(RQC_EPLAN, "leaf leg neither kept nor projected");
-            }
-            sel[i] = d;
-            full_off += (int64_t)L.data.size();
-            buf_off += (int64_t)1 << legs[i].size();
-        }
-        // lower
-        std::vector<int> root_layout;
-        p.prog = lower_tree(p.tree, legs, leaf_off, root_layout);
-        Program &pg = p.prog;
-        pg.leafbuf_elems = buf_off;
-        if ((size_t)pg.small_lds_elems * sizeof(float2) > 65536)
-            fail(RQC_EPLAN, "fused subtree needs more than 64 KiB of LDS");
-        {
-            std::vector<int> om(n_open), sm(p.batched.size());
-            for (int b = 0; b < n_open; b++) {
-                int v = net.out_var[p.open_qubits[b]];
-                auto it = std::find(root_layout.begin(), root_layout.end(), v);
-                if (it == root_layout.end()) fail(RQC_EPLAN, "open leg missing from the final tensor");
-                om[b] = (int)(it - root_layout.begin());
-            }
-            for (size_t u = 0; u < p.batched.size(); u++) {
-                auto it = std::find(root_layout.begin(), root_layout.end(), p.batched[u]);
-                if (it == root_layout.end()) fail(RQC_EPLAN, "batched leg missing from the final tensor");
-                sm[u] = (int)(it - root_layout.begin());
-            }
-            if (root_layout.size() != (size_t)n_open + p.batched.size())
-                fail(RQC_EPLAN, "final tensor has unexpected legs");
-            pg.root_open = make_map(om);
-            pg.root_slice = make_map(sm);
-            pg.n_batched = (int)p.batched.size();
-        }
-        for (auto &op : pg.permutes) p.perm_desc.push_back(make_perm_desc(op.r, op.perm));
-        // -------- device buffers
-        std::vector<float2> full((size_t)full_off);
-        {
-            size_t k = 0;
-            for (auto &L : net.leaves)
-                for (auto &x : L.data) full[k++] = make_float2(x.real(), x.imag());
-        }
-        if (!p.opts.dry_run) try {
-            p.d_full = (float2 *)p.dalloc(full.size() * sizeof(float2));
-            p.d_sel = (LeafSel *)p.dalloc(sel.size() * sizeof(LeafSel));
-            p.d_leafbuf = (float2 *)p.dalloc((size_t)buf_off * sizeof(float2));
-            p.d_arena = (float2 *)p.dalloc((size_t)std::max<int64_t>(pg.arena_elems, 64) * sizeof(float2));
-            p.d_steps = (SmallStep *)p.dalloc(std::max<size_t>(1, pg.small_steps.size()) * sizeof(SmallStep));
-            p.d_trees = (SmallTree *)p.dalloc(std::max<size_t>(1, pg.small_trees.size()) * sizeof(SmallTree));
-            p.d_acc = (double2 *)p.dalloc(((size_t)1 << n_open) * sizeof(double2));
-            HIP_OK(hipMemcpy(p.d_full, full.data(), full.size() * sizeof(float2), hipMemcpyHostToDevice));
-            HIP_OK(hipMemcpy(p.d_sel, sel.data(), sel.size() * sizeof(LeafSel), hipMemcpyHostToDevice));
-            if (!pg.small_steps.empty())
-                HIP_OK(hipMemcpy(p.d_steps, pg.small_steps.data(), pg.small_steps.size() * sizeof(SmallStep),
-                                 hipMemcpyHostToDevice));
-            if (!pg.small_trees.empty())
-                HIP_OK(hipMemcpy(p.d_trees, pg.small_trees.data(), pg.small_trees.size() * sizeof(SmallTree),
-                                 hipMemcpyHostToDevice));
-        } catch (...) {
-            p.release();
-            throw;
-        }
-        // -------- info
-        rqc_plan_info_t &I = p.info;
-        I.n_qubits = n;
-        I.n_open = n_open;
-        I.n_variables = nv;
-        I.n_sliced = (int32_t)p.sliced.size();
-        I.n_batched = (int32_t)p.batched.size();
-        I.n_partial = (int32_t)p.S.size();
-        I.n_groups = (int64_t)1 << p.looped.size();
-        I.n_slices = I.n_groups << p.batched.size();
-        I.n_partial_kept = (int64_t)p.X.size();
-        I.fidelity = p.F;
-        I.flops_per_batch = pg.flops * (double)I.n_groups;
-        I.gemm_flop_share = pg.flops > 0 ? pg.gemm_flops / pg.flops : 0.0;
-        I.bytes_per_batch = pg.bytes * (double)I.n_groups;
-        I.max_log2_tensor = pg.max_log2;
-        I.n_steps = (int32_t)p.tree.steps.size();
-        I.n_launches = (int32_t)pg.ops.size() + 2;
-        I.workspace_bytes = 0;
-        for (auto &o : p.owned) I.workspace_bytes += (int64_t)o.second;
-        I.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        plan_finish(p);
+        if (const char *d = std::getenv("RQC_DUMP_PLAN"); d && d[0] == '1') dump_plan(p);
+        p.upload();
+        p.info.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         *out = P.release();
     });
 }
@@ -533,7 +454,6 @@ rqc_status rqc_plan_profile_reset(rqc_plan *p) {
 void rqc_plan_destroy(rqc_plan *p) {
     if (!p) return;
     if (!p->opts.dry_run) (void)hipDeviceSynchronize();
-    p->release();
     delete p;
 }
 
@@ -549,115 +469,36 @@ rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64
         int dev = 0;
         HIP_OK(hipGetDevice(&dev));
         if (dev != p->device) fail(RQC_EDEVICE, "plan belongs to another device");
-        hipStream_t s = (hipStream_t)hip_stream;
-        const Program &pg = p->prog;
-        // slice groups: values of the looped legs, ascending
-        std::vector<uint64_t> groups;
         const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
         if (!slice_ids) {
-            for (uint64_t g = 0; g < ((uint64_t)1 << nl); g++) groups.push_back(g);
-        } else {
-            if (n_slices < 0) fail(RQC_EINVAL, "negative slice count");
-            std::vector<std::pair<uint64_t, uint64_t>> kv; // (looped value, batched value)
-            for (int64_t i = 0; i < n_slices; i++) {
-                uint64_t sid = slice_ids[i];
-                if (p->sliced.size() < 64 && (sid >> p->sliced.size()))
-                    fail(RQC_EINVAL, "slice id has bits beyond the sliced legs");
-                uint64_t lv = 0, bv = 0;
-                for (int u = 0; u < nl; u++) lv |= ((sid >> p->looped_bit[u]) & 1) << u;
-                for (int u = 0; u < nb; u++) bv |= ((sid >> p->batched_bit[u]) & 1) << u;
-                kv.push_back({lv, bv});
-            }
-            std::sort(kv.begin(), kv.end());
-            for (size_t i = 0; i < kv.size();) {
-                size_t j = i;
-                while (j < kv.size() && kv[j].first == kv[i].first) j++;
-                if (j - i != ((size_t)1 << nb))
-                    fail(RQC_EINVAL, "slice list must contain whole batched groups (" +
-                                         std::to_string((size_t)1 << nb) + " slices per looped value)");
-                for (size_t k = i; k < j; k++)
-                    if (kv[k].second != (uint64_t)(k - i)) fail(RQC_EINVAL, "repeated slice id");
-                groups.push_back(kv[i].first);
-                i = j;
-            }
+            execute(p, p->groups, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
+            return;
         }
-        const int n_open = (int)p->open_qubits.size();
-        const int64_t nout = (int64_t)1 << n_open;
-        const double scale = 1.0 / std::sqrt(p->F);
-        const int nfix = (int)p->fixed_qubit.size();
-        auto ptr = [&](const Buf &b) -> float2 * { return (b.kind == 0 ? p->d_arena : p->d_leafbuf) + b.off; };
-        for (int64_t bi = 0; bi < n_batches; bi++) {
-            {
-                Timer t(p, s, RQC_K_ACCUM, 0, 16.0 * nout);
-                launch_zero(p->d_acc, nout, s);
-            }
-            for (uint64_t g : groups) {
-                ProjVals vals{};
-                for (int i = 0; i < nfix; i++)
-                    if ((fixed_bits[bi] >> p->fixed_qubit[i]) & 1) vals.w[i >> 6] |= 1ull << (i & 63);
-                for (int u = 0; u < nl; u++)
-                    if ((g >> u) & 1) {
-                        int idx = nfix + u;
-                        vals.w[idx >> 6] |= 1ull << (idx & 63);
-                    }
-                {
-                    Timer t(p, s, RQC_K_LEAF, 0, 16.0 * (double)pg.leafbuf_elems);
-                    launch_leaf_select(p->d_full, p->d_leafbuf, p->d_sel, p->n_leaves, vals, s);
-                }
-                for (const Op &op : pg.ops) {
-                    switch (op.kind) {
-                    case OP_SMALL: {
-                        Timer t(p, s, RQC_K_SMALL, op.flops, op.bytes);
-                        launch_small_trees(p->d_steps, p->d_trees, (int)pg.small_trees.size(), pg.small_lds_elems,
-                                           p->d_leafbuf, p->d_arena, s);
-                        break;
-                    }
-                    case OP_STREAM: {
-                        const StreamOp &so = pg.streams[op.index];
-                        Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
-                        launch_stream(so, ptr(so.a), ptr(so.b), ptr(so.c), s);
-                        break;
-                    }
-                    case OP_PERMUTE: {
-                        const PermuteOp &po = pg.permutes[op.index];
-                        Timer t(p, s, RQC_K_PERMUTE, op.flops, op.bytes);
-                        launch_permute(p->perm_desc[op.index], ptr(po.src), ptr(po.dst), s);
-                        break;
-                    }
-                    case OP_GEMM: {
-                        const GemmOp &go = pg.gemms[op.index];
-                        GemmArgs ga;
-                        ga.A = ptr(go.a);
-                        ga.B = ptr(go.b);
-                        ga.C = ptr(go.c);
-                        ga.batch = go.batch;
-                        ga.M = go.M;
-                        ga.N = go.N;
-                        ga.K = go.K;
-                        ga.sa = go.sa;
-                        ga.sb = go.sb;
-                        ga.sc = go.sc;
-                        ga.a_kfast = go.a_kfast;
-                        ga.b_nfast = go.b_nfast;
-                        Timer t(p, s, RQC_K_GEMM, op.flops, op.bytes);
-                        launch_gemm(ga, p->opts.precision, s);
-                        break;
-                    }
-                    }
-                }
-                {
-                    Timer t(p, s, RQC_K_ACCUM, 0, 8.0 * (double)(nout << nb) + 32.0 * nout);
-                    launch_accumulate(ptr(pg.root), pg.root_open, pg.root_slice, n_open, nb, p->d_acc, s);
-                }
-            }
-            {
-                Timer t(p, s, RQC_K_FINAL, 0, 16.0 * nout + 8.0 * nout);
-                launch_finalize(p->d_acc, nout, scale, (float2 *)out_amps + bi * nout,
-                                out_f64 ? (double2 *)out_f64 + bi * nout : nullptr, s);
-            }
+        if (n_slices < 0) fail(RQC_EINVAL, "negative slice count");
+        std::vector<std::pair<uint64_t, uint64_t>> kv; // (looped value, batched value)
+        for (int64_t i = 0; i < n_slices; i++) {
+            const uint64_t sid = slice_ids[i];
+            if (p->sliced.size() < 64 && (sid >> p->sliced.size()))
+                fail(RQC_EINVAL, "slice id has bits beyond the sliced legs");
+            uint64_t lv = 0, bv = 0;
+            for (int u = 0; u < nl; u++) lv |= ((sid >> p->looped_bit[u]) & 1) << u;
+            for (int u = 0; u < nb; u++) bv |= ((sid >> p->batched_bit[u]) & 1) << u;
+            kv.push_back({lv, bv});
         }
-        HIP_OK(hipGetLastError());
-        if (p->opts.profile && p->pending.size() > 8192) p->flush_profile();
+        std::sort(kv.begin(), kv.end());
+        std::vector<uint64_t> groups;
+        for (size_t i = 0; i < kv.size();) {
+            size_t j = i;
+            while (j < kv.size() && kv[j].first == kv[i].first) j++;
+            if (j - i != ((size_t)1 << nb))
+                fail(RQC_EINVAL, "slice list must contain whole batched groups (" + std::to_string((size_t)1 << nb) +
+                                     " slices per looped value)");
+            for (size_t k = i; k < j; k++)
+                if (kv[k].second != (uint64_t)(k - i)) fail(RQC_EINVAL, "repeated slice id");
+            groups.push_back(kv[i].first);
+            i = j;
+        }
+        execute(p, groups, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
     });
 }
 
@@ -708,6 +549,64 @@ rqc_status rqc_rejection_sample(const void *amps, const uint64_t *fixed_bits, in
         return RQC_ESHORT;
     }
     return st;
+}
+
+static unsigned *kernel_amax_scratch() {
+    // two words per device for the fp16 split scaling of rqc_kernel_cgemm
+    static std::mutex mu;
+    static std::vector<unsigned *> per_dev;
+    std::lock_guard<std::mutex> lk(mu);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1, nullptr);
+    if (!per_dev[dev]) HIP_OK(hipMalloc(&per_dev[dev], 256));
+    return per_dev[dev];
+}
+
+rqc_status rqc_kernel_cgemm(const void *A, const void *B, void *C, int64_t batch, int64_t M, int64_t N, int64_t K,
+                            int32_t a_kfast, int32_t b_nfast, int32_t precision, void *hip_stream) {
+    return guard([&] {
+        if (!A || !B || !C) fail(RQC_EINVAL, "null operand");
+        auto pow2 = [](int64_t x) { return x > 0 && (x & (x - 1)) == 0; };
+        if (batch < 1 || !pow2(M) || !pow2(N) || !pow2(K) || M < 64 || N < 64 || K < 8)
+            fail(RQC_EINVAL, "GEMM needs powers of two with M, N >= 64 and K >= 8");
+        if (batch * M * N >= ((int64_t)1 << 34)) fail(RQC_EINVAL, "GEMM output too large");
+        if (precision < 0 || precision > 2) fail(RQC_EINVAL, "unknown precision");
+        check_device();
+        GemmArgs g;
+        g.A = (const float2 *)A;
+        g.B = (const float2 *)B;
+        g.C = (float2 *)C;
+        g.batch = batch;
+        g.M = M;
+        g.N = N;
+        g.K = K;
+        g.sa = M * K;
+        g.sb = K * N;
+        g.sc = M * N;
+        g.a_kfast = a_kfast ? 1 : 0;
+        g.b_nfast = b_nfast ? 1 : 0;
+        launch_gemm(g, precision, kernel_amax_scratch(), (hipStream_t)hip_stream);
+        HIP_OK(hipGetLastError());
+    });
+}
+
+rqc_status rqc_kernel_permute(const void *src, void *dst, int32_t r, const int32_t *perm, void *hip_stream) {
+    return guard([&] {
+        if (!src || !dst || !perm) fail(RQC_EINVAL, "null argument");
+        if (r < 0 || r > 34) fail(RQC_EINVAL, "rank must be 0..34");
+        std::vector<int> pv(r);
+        std::vector<char> seen(r, 0);
+        for (int i = 0; i < r; i++) {
+            if (perm[i] < 0 || perm[i] >= r || seen[perm[i]]) fail(RQC_EINVAL, "perm is not a permutation");
+            seen[perm[i]] = 1;
+            pv[i] = perm[i];
+        }
+        check_device();
+        PermDesc d = make_perm_desc(r, pv);
+        launch_permute(d, (const float2 *)src, (float2 *)dst, (hipStream_t)hip_stream);
+        HIP_OK(hipGetLastError());
+    });
 }
 
 } // extern "C"

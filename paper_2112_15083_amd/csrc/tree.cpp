@@ -8,6 +8,9 @@
 // one at a time, each chosen to minimise the total sliced cost among the legs
 // of the largest tensors (or among all legs once the memory target holds).
 #include <algorithm>
+#include <atomic>
+#include <functional>
+#include <thread>
 #include <cmath>
 #include <queue>
 #include <random>
@@ -90,6 +93,29 @@ double tree_log2_cost_sum(const Tree &t, const std::vector<Legs> &legs) {
     return mx + std::log2(acc);
 }
 
+// Time-like cost of one pairwise step: complex multiply-adds plus kTraffic per
+// element read or written.  On MI355X one complex64 element of HBM traffic
+// (8 bytes at 8 TB/s) takes as long as ~20 complex MACs on FP32 MFMA
+// (8 flops each at 157 TFLOP/s); a lower weight is used because small
+// operands are served from cache or LDS.
+static constexpr double kTraffic = 5.0;
+
+static double step_cost(int ra, int rb, int runion, int rc) {
+    return std::exp2((double)runion) +
+           kTraffic * (std::exp2((double)ra) + std::exp2((double)rb) + std::exp2((double)rc));
+}
+
+double tree_log2_time_cost(const Tree &t, const std::vector<Legs> &legs) {
+    double acc = 0;
+    for (size_t s = 0; s < t.steps.size(); s++) {
+        const Legs &A = legs[t.steps[s].first], &B = legs[t.steps[s].second];
+        Legs u = merge_union(A, B);
+        acc += step_cost((int)A.size(), (int)B.size(), (int)u.size(),
+                         (int)legs[t.n_leaves + s].size());
+    }
+    return std::log2(std::max(acc, 1.0));
+}
+
 namespace {
 struct Cand {
     double key;
@@ -99,7 +125,7 @@ struct Cand {
 } // namespace
 
 Tree greedy_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
-                 uint64_t seed, double temperature) {
+                 uint64_t seed, double temperature, double costmod) {
     const int n0 = (int)leaf_legs.size();
     std::vector<Legs> legs(leaf_legs);
     legs.reserve(2 * n0);
@@ -136,8 +162,8 @@ Tree greedy_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vect
         return out;
     };
     auto score = [&](int a, int b) {
-        double sc = std::exp2((double)out_legs(a, b).size()) - std::exp2((double)legs[a].size()) -
-                    std::exp2((double)legs[b].size());
+        double sc = std::exp2((double)out_legs(a, b).size()) -
+                    costmod * (std::exp2((double)legs[a].size()) + std::exp2((double)legs[b].size()));
         double key = (sc >= 0 ? 1 : -1) * std::log2(1.0 + std::fabs(sc));
         if (temperature > 0) key -= temperature * (-std::log(-std::log(U(rng))));
         return key;
@@ -207,6 +233,233 @@ Tree greedy_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vect
         rest.push_back(merge(std::min(a, b), std::max(a, b)));
     }
     return tree;
+}
+
+// ------------------------------------------------------------------ subtree reconfiguration
+namespace {
+constexpr int kWords = 8; // local leg universe of up to 512 legs
+struct Mask {
+    uint64_t w[kWords];
+};
+inline Mask mor(const Mask &a, const Mask &b) {
+    Mask r;
+    for (int i = 0; i < kWords; i++) r.w[i] = a.w[i] | b.w[i];
+    return r;
+}
+inline Mask mand(const Mask &a, const Mask &b) {
+    Mask r;
+    for (int i = 0; i < kWords; i++) r.w[i] = a.w[i] & b.w[i];
+    return r;
+}
+inline int mpop(const Mask &a) {
+    int c = 0;
+    for (int i = 0; i < kWords; i++) c += __builtin_popcountll(a.w[i]);
+    return c;
+}
+} // namespace
+
+Tree reconfigure_tree(const Tree &t, const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
+                      int k, int passes) {
+    const int L = t.n_leaves, ns = (int)t.steps.size();
+    if (ns < 2 || k < 3) return t;
+    const int nt = L + ns;
+    std::vector<int> ca(nt, -1), cb(nt, -1);
+    for (int s = 0; s < ns; s++) ca[L + s] = t.steps[s].first, cb[L + s] = t.steps[s].second;
+    const int root = nt - 1;
+    std::vector<int> total(n_vars, 0);
+    for (auto &l : leaf_legs)
+        for (int v : l) total[v]++;
+    std::vector<Legs> legs(nt);
+    std::vector<std::vector<int>> cnt(nt);
+    // post-order list of internal nodes
+    auto postorder = [&]() {
+        std::vector<int> order, stack{root};
+        std::vector<char> done(nt, 0);
+        while (!stack.empty()) {
+            int u = stack.back();
+            if (u < L) {
+                stack.pop_back();
+                continue;
+            }
+            if (!done[u]) {
+                done[u] = 1;
+                stack.push_back(ca[u]);
+                stack.push_back(cb[u]);
+            } else {
+                stack.pop_back();
+                order.push_back(u);
+            }
+        }
+        return order;
+    };
+    auto compute_legs = [&](const std::vector<int> &order) {
+        for (int i = 0; i < L; i++) {
+            legs[i] = leaf_legs[i];
+            cnt[i].assign(legs[i].size(), 1);
+        }
+        for (int c : order) {
+            int a = ca[c], b = cb[c];
+            const Legs &A = legs[a], &B = legs[b];
+            Legs out;
+            std::vector<int> oc;
+            size_t i = 0, j = 0;
+            while (i < A.size() || j < B.size()) {
+                int v, kk;
+                if (j >= B.size() || (i < A.size() && A[i] < B[j])) v = A[i], kk = cnt[a][i++];
+                else if (i >= A.size() || B[j] < A[i]) v = B[j], kk = cnt[b][j++];
+                else v = A[i], kk = cnt[a][i++] + cnt[b][j++];
+                if (kept[v] || kk < total[v]) out.push_back(v), oc.push_back(kk);
+            }
+            legs[c] = out;
+            cnt[c] = oc;
+        }
+    };
+    for (int pass = 0; pass < passes; pass++) {
+        std::vector<int> order = postorder();
+        compute_legs(order);
+        bool changed = false;
+        for (int tnode : order) {
+            // frontier: expand the largest internal members until k tensors
+            std::vector<int> front{ca[tnode], cb[tnode]};
+            std::vector<int> inner{tnode};
+            while ((int)front.size() < k) {
+                int best = -1;
+                for (int i = 0; i < (int)front.size(); i++)
+                    if (front[i] >= L && (best < 0 || legs[front[i]].size() > legs[front[best]].size())) best = i;
+                if (best < 0) break;
+                int u = front[best];
+                inner.push_back(u);
+                front[best] = ca[u];
+                front.push_back(cb[u]);
+            }
+            const int f = (int)front.size();
+            if (f < 3) continue;
+            // local leg universe
+            std::vector<int> uni;
+            for (int u : front) uni.insert(uni.end(), legs[u].begin(), legs[u].end());
+            std::sort(uni.begin(), uni.end());
+            uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+            if ((int)uni.size() > 64 * kWords) continue;
+            auto to_mask = [&](const Legs &l) {
+                Mask m{};
+                for (int v : l) {
+                    int i = (int)(std::lower_bound(uni.begin(), uni.end(), v) - uni.begin());
+                    if (i < (int)uni.size() && uni[i] == v) m.w[i >> 6] |= 1ull << (i & 63);
+                }
+                return m;
+            };
+            std::vector<Mask> fm(f);
+            for (int i = 0; i < f; i++) fm[i] = to_mask(legs[front[i]]);
+            const Mask outside = to_mask(legs[tnode]);
+            const int full = (1 << f) - 1;
+            std::vector<Mask> U(1 << f);
+            U[0] = Mask{};
+            for (int S = 1; S <= full; S++) {
+                int low = __builtin_ctz(S);
+                U[S] = mor(U[S & (S - 1)], fm[low]);
+            }
+            std::vector<Mask> LG(1 << f);
+            std::vector<int> lsz(1 << f);
+            for (int S = 1; S <= full; S++) {
+                LG[S] = mand(U[S], mor(outside, U[full ^ S]));
+                lsz[S] = mpop(LG[S]);
+            }
+            std::vector<double> cost(1 << f, 0.0);
+            std::vector<int> split(1 << f, 0);
+            for (int S = 1; S <= full; S++) {
+                if ((S & (S - 1)) == 0) continue;
+                int low = S & -S, rest = S ^ low;
+                double best = 1e300;
+                int bs = 0;
+                for (int sub = rest;; sub = (sub - 1) & rest) {
+                    int S1 = low | sub, S2 = S ^ S1;
+                    if (S2) {
+                        double c = cost[S1] + cost[S2] +
+                                   step_cost(lsz[S1], lsz[S2], mpop(mor(LG[S1], LG[S2])), lsz[S]);
+                        if (c < best) best = c, bs = S1;
+                    }
+                    if (sub == 0) break;
+                }
+                cost[S] = best;
+                split[S] = bs;
+            }
+            // old cost of the same subtree
+            double old = 0;
+            for (int u : inner)
+                old += step_cost((int)legs[ca[u]].size(), (int)legs[cb[u]].size(),
+                                 (int)merge_union(legs[ca[u]], legs[cb[u]]).size(), (int)legs[u].size());
+            if (cost[full] >= old * (1 - 1e-9)) continue;
+            // rebuild: reuse the inner node ids, tnode stays the subtree root
+            std::vector<int> ids(inner.begin() + 1, inner.end());
+            std::function<int(int, bool)> build = [&](int S, bool top) -> int {
+                if ((S & (S - 1)) == 0) return front[__builtin_ctz(S)];
+                int id;
+                if (top) id = tnode;
+                else {
+                    id = ids.back();
+                    ids.pop_back();
+                }
+                int S1 = split[S];
+                int a = build(S1, false), b = build(S ^ S1, false);
+                ca[id] = a;
+                cb[id] = b;
+                Legs l;
+                for (int i = 0; i < (int)uni.size(); i++)
+                    if ((LG[S].w[i >> 6] >> (i & 63)) & 1) l.push_back(uni[i]);
+                legs[id] = l;
+                return id;
+            };
+            build(full, true);
+            changed = true;
+            // counts of the rebuilt nodes are refreshed at the next pass
+        }
+        if (!changed) break;
+    }
+    // back to SSA order
+    std::vector<int> order = postorder();
+    std::vector<int> newid(nt, -1);
+    for (int i = 0; i < L; i++) newid[i] = i;
+    Tree out;
+    out.n_leaves = L;
+    for (int c : order) {
+        out.steps.push_back({newid[ca[c]], newid[cb[c]]});
+        newid[c] = L + (int)out.steps.size() - 1;
+    }
+    return out;
+}
+
+SearchResult search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
+                         const std::vector<char> &forbidden, const std::vector<int> *user_sliced,
+                         int max_log2_tensor, int n_target, int trials, uint64_t seed) {
+    std::vector<SearchResult> res(trials);
+    std::vector<char> none(n_vars, 0);
+    auto run = [&](int tr) {
+        std::mt19937_64 rng(seed * 0x9E3779B97F4A7C15ull + (uint64_t)tr);
+        std::uniform_real_distribution<double> U(0.0, 1.0);
+        double temp = tr == 0 ? 0.0 : 0.05 + 0.95 * U(rng);
+        double costmod = tr == 0 ? 1.0 : 0.5 + 1.5 * U(rng);
+        Tree t = greedy_tree(leaf_legs, n_vars, kept, rng(), temp, costmod);
+        t = reconfigure_tree(t, leaf_legs, n_vars, kept, 8, 3);
+        auto legs = tree_legs(t, leaf_legs, n_vars, none, kept);
+        std::vector<int> sl =
+            user_sliced ? *user_sliced : greedy_slice(t, legs, n_vars, forbidden, max_log2_tensor, n_target);
+        std::vector<char> rem(n_vars, 0);
+        for (int v : sl) rem[v] = 1;
+        auto legs2 = tree_legs(t, leaf_legs, n_vars, rem, kept);
+        res[tr] = {t, sl, tree_log2_time_cost(t, legs2) + (double)sl.size()};
+    };
+    int nth = (int)std::max(1u, std::min<unsigned>(16u, std::thread::hardware_concurrency()));
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int i = 0; i < std::min(nth, trials); i++)
+        pool.emplace_back([&] {
+            for (int tr = next++; tr < trials; tr = next++) run(tr);
+        });
+    for (auto &th : pool) th.join();
+    int best = 0;
+    for (int tr = 1; tr < trials; tr++)
+        if (res[tr].log2cost < res[best].log2cost - 1e-9) best = tr;
+    return res[best];
 }
 
 std::vector<int> greedy_slice(const Tree &t, const std::vector<Legs> &legs, int n_vars,

@@ -82,6 +82,9 @@ _sig = {
     "rqc_plan_profile": [_P, ctypes.POINTER(Profile)],
     "rqc_plan_profile_reset": [_P],
     "rqc_contract_amplitudes": [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P],
+    "rqc_kernel_cgemm": [_P, _P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
+    "rqc_kernel_permute": [_P, _P, ctypes.c_int32, _P, _P],
     "rqc_rejection_sample": [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                              ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
@@ -261,6 +264,15 @@ def rejection_sample(amps, fixed_bits, open_qubits, n_qubits, n_samples, out_sam
                                             _ptr(out_samples), ctypes.byref(n_out), ctypes.byref(st),
                                             _stream(stream)), allow=(ESHORT,))
     return n_out.value, st.as_dict(), code
+
+
+def kernel_cgemm(A, B, C, batch, M, N, K, a_kfast=1, b_nfast=1, precision=C64, stream=None):
+    _check(_lib.rqc_kernel_cgemm(_ptr(A), _ptr(B), _ptr(C), batch, M, N, K, a_kfast, b_nfast, precision,
+                                 _stream(stream)))
+
+
+def kernel_permute(src, dst, perm, stream=None):
+    _check(_lib.rqc_kernel_permute(_ptr(src), _ptr(dst), len(perm), _i32(list(perm)), _stream(stream)))
 
 
 def plan_destroy(p: Plan):
