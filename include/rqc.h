@@ -204,6 +204,9 @@ rqc_status rqc_plan_partial(const rqc_plan *p, int32_t *S, int32_t capS, uint64_
                             double *R, int64_t capR);
 rqc_status rqc_plan_profile(const rqc_plan *p, rqc_profile_t *out);
 rqc_status rqc_plan_profile_reset(rqc_plan *p);
+/* Free a plan.  No work using the plan may still be pending on any stream when
+   its workspace came from a caller-supplied allocator; with the default
+   allocator the device is synchronised first. */
 void rqc_plan_destroy(rqc_plan *p);
 
 /*

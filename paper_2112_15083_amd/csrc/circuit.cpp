@@ -180,14 +180,47 @@ Network build_network(const Circuit &c) {
             net.gate_inputs.push_back({a});
             L.legs = {a, v};
             L.data.resize(4);
-            for (int x = 0; x < 4; x++) L.data[x] = cf(u[(x >> 1) & 1][x & 1]);
+            // Stored as lambda * U with every entry exact in FP32, so rounding the
+            // leaves leaves no systematic norm bias; 1/lambda is applied in FP64.
+            // sqrt(X), sqrt(Y): entries are (1/sqrt 2) * {1, -1, -i}: lambda =
+            // fl32(1/sqrt 2) * sqrt 2.  sqrt(W): diagonal 1/sqrt 2, off-diagonal
+            // (+-1 +- i)/2; with o = 9093512 / 2^24 and d = 12860168 / 2^24
+            // (d / o = 12860168 / 9093512, a convergent of sqrt 2 scaled by 8,
+            // exact to 3e-14), lambda = 2 o.
+            double lam;
+            if (g.kind == G_SW) lam = 2.0 * (9093512.0 / 16777216.0);
+            else lam = (double)(float)(1.0 / std::sqrt(2.0)) * std::sqrt(2.0);
+            for (int x = 0; x < 4; x++) {
+                cd e = lam * u[(x >> 1) & 1][x & 1];
+                L.data[x] = cf((float)e.real(), (float)e.imag());
+            }
+            if (g.kind == G_SW) {
+                const float d = 12860168.0f / 16777216.0f;
+                L.data[0] = cf(d, 0.f);
+                L.data[3] = cf(d, 0.f);
+            }
+            L.scale = lam;
             cur[g.q[0]] = v;
         } else if (g.swap_like()) {
             const double ph = M_PI * (double)g.pnum / (double)g.pden;
             int a = cur[g.q[0]], b = cur[g.q[1]];
             net.gate_inputs.push_back({a, b});
             L.legs = {a, b};
-            L.data = {cf(1, 0), cf(0, -1), cf(0, -1), cf((float)std::cos(ph), (float)-std::sin(ph))};
+            // e^{-i phi} as the complex64 value of least |.|^2 - 1 within a few
+            // ulps of the rounded phase, so repeated use adds no norm drift
+            float bc = (float)std::cos(ph), bs = (float)-std::sin(ph);
+            double best = 1e300;
+            const float c0 = bc, s0 = bs;
+            for (int i = -4; i <= 4; i++)
+                for (int j = -4; j <= 4; j++) {
+                    float c = c0, s = s0;
+                    for (int t = 0; t < std::abs(i); t++) c = std::nextafter(c, i > 0 ? 2.f : -2.f);
+                    for (int t = 0; t < std::abs(j); t++) s = std::nextafter(s, j > 0 ? 2.f : -2.f);
+                    double err = std::fabs((double)c * c + (double)s * s - 1.0) +
+                                 std::fabs(std::atan2((double)s, (double)c) + ph) * 0.5;
+                    if (err < best) best = err, bc = c, bs = s;
+                }
+            L.data = {cf(1, 0), cf(0, -1), cf(0, -1), cf(bc, bs)};
             std::swap(cur[g.q[0]], cur[g.q[1]]);
         } else {
             cd u[4][4];

@@ -44,6 +44,7 @@ Circuit parse_circuit(const char *text, size_t len);
 struct Leaf {
     std::vector<int> legs; // variable ids; legs[0] is bit 0 of the element index
     std::vector<cf> data;  // 2^legs.size() values (input variables already fixed to 0)
+    double scale = 1.0;    // data = scale * (exact tensor), up to complex64 rounding
 };
 
 struct Network {
@@ -133,10 +134,14 @@ struct SmallTree {
     int first_step, n_steps;
 };
 
-struct StreamOp {   // C[x] = sum_y A[ax(x)+ay(y)] * B[bx(x)+by(y)]
+// C[x] = sum_y A[ax(x)+ay(y)] * B[bx(x)+by(y)].  The C index x splits into
+// the bits of B's new legs (f, nf bits) and the rest (r, nr bits):
+// x = xC(r) + fC(f), A offset = rA(r) + yA(y), B offset = rB(r) + fB(f) + yB(y).
+enum { SM_RA = 0, SM_RB, SM_RC, SM_FB, SM_FC, SM_YA, SM_YB, SM_COUNT };
+struct StreamOp {
     Buf a, b, c;
-    int rc, kc;
-    BitMap ax, bx, ay, by;
+    int rc, kc, nr, nf;
+    BitMap m[SM_COUNT];
 };
 
 struct PermuteOp {  // dst[pi(x)] = src[x]
@@ -220,6 +225,7 @@ struct PlanCore {
     std::vector<uint64_t> X;                   // kept partial indices, in selection order
     std::vector<double> R;
     double F = 1.0;
+    double kappa = 1.0;                        // product of 1/leaf.scale (applied in FP64 at the end)
     std::vector<uint64_t> groups;              // default slice groups: looped-leg values
     Program prog;
     std::vector<LeafSel> sel;

@@ -81,51 +81,117 @@ void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int 
 }
 
 // ------------------------------------------------------------------ streaming contraction
-struct StreamArgs {
-    const float2 *a;
-    const float2 *b;
-    float2 *c;
-    int64_t n;
-    int kc;
-    BitMap ax, bx, ay, by;
-};
-
-__global__ void __launch_bounds__(256) k_stream(StreamArgs p) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int nK = 1 << p.kc;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < p.n; x += stride) {
-        const int64_t ax = map_apply(p.ax, x), bx = map_apply(p.bx, x);
-        float2 acc = make_float2(0.f, 0.f);
-        for (int y = 0; y < nK; y++) cmac(acc, p.a[ax + map_apply(p.ay, y)], p.b[bx + map_apply(p.by, y)]);
-        p.c[x] = acc;
+// Register-blocked form: a thread owns one r (the C index without B's new
+// legs), loads its 2^kc operand values of A once and writes all 2^nf outputs
+// that share them, so A is read from HBM once.  Threads of a block take 256
+// consecutive r; the low 8 bits of r map through per-thread offsets, the high
+// bits through one uniform map per chunk.
+template <int KMAX, int FMAX>
+__global__ void __launch_bounds__(256) k_stream_rb(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                   float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
+                                                   int kc, int nf) {
+    __shared__ int64_t tyA[KMAX], tyB[KMAX], tfB[FMAX], tfC[FMAX];
+    const int tid = threadIdx.x;
+    const int nK = 1 << kc, nF = 1 << nf;
+    if (tid < nK) {
+        tyA[tid] = map_apply(maps[SM_YA], tid);
+        tyB[tid] = map_apply(maps[SM_YB], tid);
+    }
+    if (tid < nF) {
+        tfB[tid] = map_apply(maps[SM_FB], tid);
+        tfC[tid] = map_apply(maps[SM_FC], tid);
+    }
+    __syncthreads();
+    const int lo_bits = nr < 8 ? nr : 8;
+    if (tid >= (1 << lo_bits)) return;
+    const int64_t a_lo = map_apply(maps[SM_RA], tid), b_lo = map_apply(maps[SM_RB], tid),
+                  c_lo = map_apply(maps[SM_RC], tid);
+    const int64_t n_chunks = (int64_t)1 << (nr - lo_bits);
+    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+        const int64_t r0 = ch << lo_bits;
+        const int64_t ab = map_apply(maps[SM_RA], r0) + a_lo;
+        const int64_t bb = map_apply(maps[SM_RB], r0) + b_lo;
+        const int64_t cb = map_apply(maps[SM_RC], r0) + c_lo;
+        float2 a[KMAX];
+#pragma unroll
+        for (int y = 0; y < KMAX; y++)
+            if (y < nK) a[y] = A[ab + tyA[y]];
+#pragma unroll
+        for (int f = 0; f < FMAX; f++) {
+            if (f < nF) {
+                float2 acc = make_float2(0.f, 0.f);
+                const float2 *bp = B + bb + tfB[f];
+#pragma unroll
+                for (int y = 0; y < KMAX; y++)
+                    if (y < nK) cmac(acc, a[y], bp[tyB[y]]);
+                C[cb + tfC[f]] = acc;
+            }
+        }
     }
 }
 
-void launch_stream(const StreamOp &op, const float2 *a, const float2 *b, float2 *c, hipStream_t s) {
-    StreamArgs p;
-    p.a = a;
-    p.b = b;
-    p.c = c;
-    p.n = (int64_t)1 << op.rc;
-    p.kc = op.kc;
-    p.ax = op.ax;
-    p.bx = op.bx;
-    p.ay = op.ay;
-    p.by = op.by;
-    const int threads = 256;
-    int64_t blocks = (p.n + threads - 1) / threads;
-    if (blocks > 256 * 64) blocks = 256 * 64;
-    hipLaunchKernelGGL(k_stream, dim3((unsigned)blocks), dim3(threads), 0, s, p);
+// General form for long contracted or new-leg dimensions: one output per
+// thread and iteration, contracted offsets tabulated in LDS (low 10 bits) and
+// mapped per high part.
+__global__ void __launch_bounds__(256) k_stream_gen(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                    float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
+                                                    int kc, int nf) {
+    __shared__ int64_t tyA[1024], tyB[1024];
+    const int tid = threadIdx.x;
+    const int ylo = kc < 10 ? kc : 10;
+    const int nylo = 1 << ylo;
+    const int64_t nyhi = (int64_t)1 << (kc - ylo);
+    for (int i = tid; i < nylo; i += blockDim.x) {
+        tyA[i] = map_apply(maps[SM_YA], i);
+        tyB[i] = map_apply(maps[SM_YB], i);
+    }
+    __syncthreads();
+    const int64_t n = (int64_t)1 << (nr + nf);
+    const int64_t nfm = ((int64_t)1 << nf) - 1;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + tid; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t f = x & nfm, r = x >> nf;
+        const int64_t ab = map_apply(maps[SM_RA], r);
+        const int64_t bb = map_apply(maps[SM_RB], r) + map_apply(maps[SM_FB], f);
+        float2 acc = make_float2(0.f, 0.f);
+        for (int64_t yh = 0; yh < nyhi; yh++) {
+            const int64_t ah = ab + map_apply(maps[SM_YA], yh << ylo), bh = bb + map_apply(maps[SM_YB], yh << ylo);
+            for (int yl = 0; yl < nylo; yl++) cmac(acc, A[ah + tyA[yl]], B[bh + tyB[yl]]);
+        }
+        C[map_apply(maps[SM_RC], r) + map_apply(maps[SM_FC], f)] = acc;
+    }
+}
+
+void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
+                   hipStream_t s) {
+    const int lo = op.nr < 8 ? op.nr : 8;
+    const int64_t chunks = (int64_t)1 << (op.nr - lo);
+    const unsigned blocks = (unsigned)std::min<int64_t>(chunks, 256 * 16);
+    const dim3 g(blocks), t(256);
+    if (op.kc <= 2 && op.nf <= 2) hipLaunchKernelGGL((k_stream_rb<4, 4>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
+    else if (op.kc <= 4 && op.nf <= 2) hipLaunchKernelGGL((k_stream_rb<16, 4>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
+    else if (op.kc <= 2 && op.nf <= 4) hipLaunchKernelGGL((k_stream_rb<4, 16>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
+    else if (op.kc <= 4 && op.nf <= 4) hipLaunchKernelGGL((k_stream_rb<16, 16>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
+    else {
+        const int64_t n = (int64_t)1 << op.rc;
+        const unsigned gb = (unsigned)std::min<int64_t>((n + 255) / 256, 256 * 64);
+        hipLaunchKernelGGL(k_stream_gen, dim3(gb), t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
+    }
 }
 
 // ------------------------------------------------------------------ permute
 PermDesc make_perm_desc(int r, const std::vector<int> &perm) {
     PermDesc d;
+    // tile = the low 5 source bits, the source bits of the low 5 destination
+    // bits, then more low source bits up to 2^10 elements
     const int t = r < 5 ? r : 5;
     std::vector<char> inT(r, 0);
     for (int i = 0; i < t; i++) inT[i] = 1;
     for (int i = 0; i < r; i++)
         if (perm[i] < t) inT[i] = 1;
+    int cnt = 0;
+    for (int i = 0; i < r; i++) cnt += inT[i];
+    for (int i = 0; i < r && cnt < 10; i++)
+        if (!inT[i]) inT[i] = 1, cnt++;
     std::vector<int> T, tb;
     for (int i = 0; i < r; i++) (inT[i] ? T : tb).push_back(i);
     d.tile_log = (int)T.size();
@@ -147,25 +213,46 @@ PermDesc make_perm_desc(int r, const std::vector<int> &perm) {
     return d;
 }
 
-__global__ void __launch_bounds__(256) k_permute(PermDesc d, const float2 *__restrict__ src, float2 *__restrict__ dst) {
+// One tile (at most 1024 elements) per iteration: read in source order
+// (coalesced on the low source bits), write in destination order (coalesced on
+// the low destination bits) through a padded LDS tile.
+__global__ void __launch_bounds__(256) k_permute(const PermDesc *__restrict__ dp, const float2 *__restrict__ src,
+                                                 float2 *__restrict__ dst) {
     __shared__ float2 tile[1024 + 32];
+    const PermDesc &d = *dp;
     const int n = 1 << d.tile_log;
+    const int tid = threadIdx.x;
+    int64_t rd[4], wd[4];
+    int wl[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int i = tid + 256 * k;
+        rd[k] = i < n ? map_apply(d.rd, i) : 0;
+        wd[k] = i < n ? map_apply(d.wr_dst, i) : 0;
+        const int l = i < n ? (int)map_apply(d.wr_lds, i) : 0;
+        wl[k] = l + (l >> 5);
+    }
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         const int64_t bs = map_apply(d.tile_src, t), bd = map_apply(d.tile_dst, t);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) tile[i + (i >> 5)] = src[bs + map_apply(d.rd, i)];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = tid + 256 * k;
+            if (i < n) tile[i + (i >> 5)] = src[bs + rd[k]];
+        }
         __syncthreads();
-        for (int w = threadIdx.x; w < n; w += blockDim.x) {
-            const int l = (int)map_apply(d.wr_lds, w);
-            dst[bd + map_apply(d.wr_dst, w)] = tile[l + (l >> 5)];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = tid + 256 * k;
+            if (i < n) dst[bd + wd[k]] = tile[wl[k]];
         }
         __syncthreads();
     }
 }
 
-void launch_permute(const PermDesc &d, const float2 *src, float2 *dst, hipStream_t s) {
-    int64_t blocks = d.n_tiles;
+void launch_permute(const PermDesc *d_desc, int64_t n_tiles, const float2 *src, float2 *dst, hipStream_t s) {
+    int64_t blocks = n_tiles;
     if (blocks > 256 * 32) blocks = 256 * 32;
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s, d, src, dst);
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s, d_desc, src, dst);
 }
 
 // ------------------------------------------------------------------ complex GEMM, FP32 MFMA
@@ -535,25 +622,27 @@ void launch_gemm(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s
 }
 
 // ------------------------------------------------------------------ FP64 accumulation
-__global__ void __launch_bounds__(256) k_accumulate(const float2 *__restrict__ root, BitMap om, BitMap sm, int64_t n,
-                                                    int64_t ns, double2 *__restrict__ acc) {
+// acc[x] += sum over batched slices s (ascending) of root[open(x) + slice(s)],
+// one add at a time in FP64, so the result does not depend on how slices are
+// grouped into launches.
+__global__ void __launch_bounds__(256) k_accumulate(const float2 *__restrict__ root, const BitMap *__restrict__ maps,
+                                                    int64_t n, int64_t ns, double2 *__restrict__ acc) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    const int64_t ox = map_apply(om, x);
+    const int64_t ox = map_apply(maps[0], x);
     double2 a = acc[x];
     for (int64_t s = 0; s < ns; s++) {
-        const float2 c = root[ox + map_apply(sm, s)];
+        const float2 c = root[ox + map_apply(maps[1], s)];
         a.x += (double)c.x;
         a.y += (double)c.y;
     }
     acc[x] = a;
 }
 
-void launch_accumulate(const float2 *root, const BitMap &open_map, const BitMap &slice_map, int n_open,
-                       int n_batched, double2 *acc, hipStream_t s) {
+void launch_accumulate(const float2 *root, const BitMap *d_maps, int n_open, int n_batched, double2 *acc,
+                       hipStream_t s) {
     const int64_t n = (int64_t)1 << n_open, ns = (int64_t)1 << n_batched;
-    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, root, open_map, slice_map,
-                       n, ns, acc);
+    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, root, d_maps, n, ns, acc);
 }
 
 __global__ void k_zero(double2 *p, int64_t n) {

@@ -36,12 +36,16 @@ void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_se
                         ProjVals vals, hipStream_t s);
 void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int n_trees, int lds_elems,
                         const float2 *leafbuf, float2 *arena, hipStream_t s);
-void launch_stream(const StreamOp &op, const float2 *a, const float2 *b, float2 *c, hipStream_t s);
-void launch_permute(const PermDesc &d, const float2 *src, float2 *dst, hipStream_t s);
+// d_maps: the op's SM_COUNT bit maps in device memory
+void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
+                   hipStream_t s);
+// d_desc: the permute descriptor in device memory
+void launch_permute(const PermDesc *d_desc, int64_t n_tiles, const float2 *src, float2 *dst, hipStream_t s);
 // precision: rqc_precision; amax: two device words of scratch (fp16 scaling)
 void launch_gemm(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s);
-void launch_accumulate(const float2 *root, const BitMap &open_map, const BitMap &slice_map, int n_open,
-                       int n_batched, double2 *acc, hipStream_t s);
+// d_maps[0]: open index -> root offset, d_maps[1]: batched slice index -> root offset
+void launch_accumulate(const float2 *root, const BitMap *d_maps, int n_open, int n_batched, double2 *acc,
+                       hipStream_t s);
 void launch_zero(double2 *acc, int64_t n, hipStream_t s);
 void launch_finalize(const double2 *acc, int64_t n, double scale, float2 *out, double2 *out64,
                      hipStream_t s);

@@ -305,16 +305,31 @@ struct Lowerer {
         op.c = materialise(t);
         op.rc = (int)LC.size();
         op.kc = (int)con.size();
-        std::vector<int> ax(LC.size()), bx(LC.size()), ay(con.size()), by(con.size());
-        for (size_t j = 0; j < LC.size(); j++) ax[j] = pos_in(LA, LC[j]), bx[j] = pos_in(LB, LC[j]);
+        std::vector<int> rest, fpos;
+        for (size_t j = 0; j < LC.size(); j++)
+            (std::find(newb.begin(), newb.end(), LC[j]) != newb.end() ? fpos : rest).push_back((int)j);
+        op.nr = (int)rest.size();
+        op.nf = (int)fpos.size();
+        std::vector<int> ra(rest.size()), rb(rest.size()), rcm(rest.size()), fb(fpos.size()), fc(fpos.size());
+        for (size_t j = 0; j < rest.size(); j++) {
+            ra[j] = pos_in(LA, LC[rest[j]]);
+            rb[j] = pos_in(LB, LC[rest[j]]);
+            rcm[j] = rest[j];
+        }
+        for (size_t j = 0; j < fpos.size(); j++) fb[j] = pos_in(LB, LC[fpos[j]]), fc[j] = fpos[j];
+        std::vector<int> ay(con.size()), by(con.size());
         for (size_t j = 0; j < con.size(); j++) ay[j] = pos_in(LA, con[j]), by[j] = pos_in(LB, con[j]);
-        op.ax = make_map(ax);
-        op.bx = make_map(bx);
-        op.ay = make_map(ay);
-        op.by = make_map(by);
+        op.m[SM_RA] = make_map(ra);
+        op.m[SM_RB] = make_map(rb);
+        op.m[SM_RC] = make_map(rcm);
+        op.m[SM_FB] = make_map(fb);
+        op.m[SM_FC] = make_map(fc);
+        op.m[SM_YA] = make_map(ay);
+        op.m[SM_YB] = make_map(by);
         double f = 8.0 * std::exp2((double)(LC.size() + con.size()));
         double by_ = 8.0 * (double)(size_of(a) + size_of(b) + size_of(t));
         prog.streams.push_back(op);
+        (void)set_of;
         prog.ops.push_back({OP_STREAM, (int)prog.streams.size() - 1, f, by_});
         prog.flops += f;
         prog.bytes += by_;

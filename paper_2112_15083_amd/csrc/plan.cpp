@@ -314,7 +314,13 @@ void plan_finish(PlanCore &p) {
     }
     p.full.clear();
     p.full.reserve((size_t)full_off);
-    for (auto &L : sp.leaves) p.full.insert(p.full.end(), L.data.begin(), L.data.end());
+    double log2_kappa = 0;
+    for (auto &L : sp.leaves) {
+        p.full.insert(p.full.end(), L.data.begin(), L.data.end());
+        log2_kappa -= std::log2(L.scale);
+    }
+    p.kappa = std::exp2(log2_kappa);
+    if (!(p.kappa > 0) || !std::isfinite(p.kappa)) fail(RQC_EPLAN, "leaf scale product out of range");
     std::vector<int> root_layout;
     p.prog = lower_tree(p.tree, legs, leaf_off, root_layout);
     Program &pg = p.prog;

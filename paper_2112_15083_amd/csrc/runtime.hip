@@ -61,7 +61,10 @@ struct rqc_plan : PlanCore {
     SmallStep *d_steps = nullptr;
     SmallTree *d_trees = nullptr;
     double2 *d_acc = nullptr;
-    unsigned *d_amax = nullptr; // operand maxima for the fp16 split scaling
+    unsigned *d_amax = nullptr;  // operand maxima for the fp16 split scaling
+    BitMap *d_smaps = nullptr;   // SM_COUNT maps per streaming op
+    BitMap *d_rmaps = nullptr;   // root maps: open index, batched slice index
+    PermDesc *d_perm = nullptr;  // permute descriptors
     // profiling
     rqc_profile_t prof{};
     std::vector<PendingEvent> pending;
@@ -135,6 +138,16 @@ struct rqc_plan : PlanCore {
             d_trees = (SmallTree *)dalloc(std::max<size_t>(1, pg.small_trees.size()) * sizeof(SmallTree));
             d_acc = (double2 *)dalloc(((size_t)1 << spec.open_vars.size()) * sizeof(double2));
             d_amax = (unsigned *)dalloc(256);
+            std::vector<BitMap> sm;
+            for (auto &so : pg.streams) sm.insert(sm.end(), so.m, so.m + SM_COUNT);
+            d_smaps = (BitMap *)dalloc(std::max<size_t>(1, sm.size()) * sizeof(BitMap));
+            if (!sm.empty()) HIP_OK(hipMemcpy(d_smaps, sm.data(), sm.size() * sizeof(BitMap), hipMemcpyHostToDevice));
+            BitMap rm[2] = {pg.root_open, pg.root_slice};
+            d_rmaps = (BitMap *)dalloc(sizeof(rm));
+            HIP_OK(hipMemcpy(d_rmaps, rm, sizeof(rm), hipMemcpyHostToDevice));
+            d_perm = (PermDesc *)dalloc(std::max<size_t>(1, perm_desc.size()) * sizeof(PermDesc));
+            if (!perm_desc.empty())
+                HIP_OK(hipMemcpy(d_perm, perm_desc.data(), perm_desc.size() * sizeof(PermDesc), hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(d_full, f.data(), f.size() * sizeof(float2), hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(d_sel, sel.data(), sel.size() * sizeof(LeafSel), hipMemcpyHostToDevice));
             if (!pg.small_steps.empty())
@@ -220,7 +233,7 @@ void execute(rqc_plan *p, const std::vector<uint64_t> &groups, const uint64_t *f
     const int n_open = (int)p->spec.open_vars.size();
     const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
     const int64_t nout = (int64_t)1 << n_open;
-    const double scale = 1.0 / std::sqrt(p->F);
+    const double scale = p->kappa / std::sqrt(p->F);
     const int nfix = (int)p->spec.fixed_vars.size();
     auto ptr = [&](const Buf &b) -> float2 * { return (b.kind == 0 ? p->d_arena : p->d_leafbuf) + b.off; };
     for (int64_t bi = 0; bi < n_batches; bi++) {
@@ -252,13 +265,13 @@ void execute(rqc_plan *p, const std::vector<uint64_t> &groups, const uint64_t *f
                 case OP_STREAM: {
                     const StreamOp &so = pg.streams[op.index];
                     Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
-                    launch_stream(so, ptr(so.a), ptr(so.b), ptr(so.c), s);
+                    launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c), s);
                     break;
                 }
                 case OP_PERMUTE: {
                     const PermuteOp &po = pg.permutes[op.index];
                     Timer t(p, s, RQC_K_PERMUTE, op.flops, op.bytes);
-                    launch_permute(p->perm_desc[op.index], ptr(po.src), ptr(po.dst), s);
+                    launch_permute(p->d_perm + op.index, p->perm_desc[op.index].n_tiles, ptr(po.src), ptr(po.dst), s);
                     break;
                 }
                 case OP_GEMM: {
@@ -284,7 +297,7 @@ void execute(rqc_plan *p, const std::vector<uint64_t> &groups, const uint64_t *f
             }
             {
                 Timer t(p, s, RQC_K_ACCUM, 0, 8.0 * (double)(nout << nb) + 32.0 * nout);
-                launch_accumulate(ptr(pg.root), pg.root_open, pg.root_slice, n_open, nb, p->d_acc, s);
+                launch_accumulate(ptr(pg.root), p->d_rmaps, n_open, nb, p->d_acc, s);
             }
         }
         {
@@ -453,7 +466,9 @@ rqc_status rqc_plan_profile_reset(rqc_plan *p) {
 
 void rqc_plan_destroy(rqc_plan *p) {
     if (!p) return;
-    if (!p->opts.dry_run) (void)hipDeviceSynchronize();
+    // with the library's own hipMalloc workspace, wait for the device before
+    // freeing; a caller-supplied allocator owns that ordering
+    if (!p->opts.dry_run && !p->opts.alloc) (void)hipDeviceSynchronize();
     delete p;
 }
 
@@ -604,8 +619,21 @@ rqc_status rqc_kernel_permute(const void *src, void *dst, int32_t r, const int32
         }
         check_device();
         PermDesc d = make_perm_desc(r, pv);
-        launch_permute(d, (const float2 *)src, (float2 *)dst, (hipStream_t)hip_stream);
+        // descriptor in device memory, one slot per device; the copy is ordered
+        // on the caller's stream before the kernel that reads it
+        static std::mutex mu;
+        static std::vector<PermDesc *> slot;
+        std::lock_guard<std::mutex> lk(mu);
+        int dev = 0;
+        HIP_OK(hipGetDevice(&dev));
+        if ((int)slot.size() <= dev) slot.resize(dev + 1, nullptr);
+        if (!slot[dev]) HIP_OK(hipMalloc(&slot[dev], sizeof(PermDesc)));
+        hipStream_t s = (hipStream_t)hip_stream;
+        HIP_OK(hipStreamSynchronize(s));
+        HIP_OK(hipMemcpy(slot[dev], &d, sizeof(d), hipMemcpyHostToDevice));
+        launch_permute(slot[dev], d.n_tiles, (const float2 *)src, (float2 *)dst, s);
         HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(s));
     });
 }
 
