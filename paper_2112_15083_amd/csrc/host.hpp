@@ -137,10 +137,16 @@ struct SmallTree {
 // C[x] = sum_y A[ax(x)+ay(y)] * B[bx(x)+by(y)].  The C index x splits into
 // the bits of B's new legs (f, nf bits) and the rest (r, nr bits):
 // x = xC(r) + fC(f), A offset = rA(r) + yA(y), B offset = rB(r) + fB(f) + yB(y).
-enum { SM_RA = 0, SM_RB, SM_RC, SM_FB, SM_FC, SM_YA, SM_YB, SM_COUNT };
+// Tiled form: a tile is 2^tile_l consecutive r; its A operands are the
+// 2^(tile_l+kc) elements e (bits: the A positions of r's low bits and of y, in
+// ascending order), staged through LDS: A offset = rA(r0) + EA(e), tile slot of
+// (r, y) = RE(r_low) + YE(y); outputs likewise with C offset = rC(r0) + EC(e'),
+// slot of (r, f) = RE2(r_low) + FE(f).
+enum { SM_RA = 0, SM_RB, SM_RC, SM_FB, SM_FC, SM_YA, SM_YB, SM_EA, SM_RE, SM_YE, SM_EC, SM_RE2, SM_FE, SM_COUNT };
 struct StreamOp {
     Buf a, b, c;
     int rc, kc, nr, nf;
+    int tile_l = -1; // >= 0: tiled kernel with 2^tile_l r per tile
     BitMap m[SM_COUNT];
 };
 
@@ -227,6 +233,7 @@ struct PlanCore {
     double F = 1.0;
     double kappa = 1.0;                        // product of 1/leaf.scale (applied in FP64 at the end)
     std::vector<uint64_t> groups;              // default slice groups: looped-leg values
+    uint64_t n_group_range = 0;                // if non-zero: the default groups are 0 .. n-1
     Program prog;
     std::vector<LeafSel> sel;
     std::vector<cf> full;                      // leaf store

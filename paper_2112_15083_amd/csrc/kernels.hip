@@ -161,8 +161,88 @@ __global__ void __launch_bounds__(256) k_stream_gen(const float2 *__restrict__ A
     }
 }
 
+// LDS-tiled form (see StreamOp): loads and stores follow the memory order of A
+// and C, so both are coalesced whatever the leg order; the compute phase reads
+// LDS through an XOR swizzle that keeps strided slot patterns conflict-free.
+__device__ __forceinline__ int swz(int e) { return e ^ ((e >> 5) & 31); }
+
+template <int KMAX, int FMAX>
+__global__ void __launch_bounds__(256) k_stream_tile(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                     float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
+                                                     int kc, int nf, int L) {
+    __shared__ float2 TA[2048], TC[2048];
+    __shared__ int tyE[KMAX], tfE[FMAX];
+    __shared__ int64_t tyB[KMAX], tfB[FMAX];
+    const int tid = threadIdx.x;
+    const int nK = 1 << kc, nF = 1 << nf;
+    if (tid < nK) {
+        tyE[tid] = (int)map_apply(maps[SM_YE], tid);
+        tyB[tid] = map_apply(maps[SM_YB], tid);
+    }
+    if (tid < nF) {
+        tfE[tid] = (int)map_apply(maps[SM_FE], tid);
+        tfB[tid] = map_apply(maps[SM_FB], tid);
+    }
+    const int nA = 1 << (L + kc), nC = 1 << (L + nf), nR = 1 << L;
+    int64_t offA[8], offC[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int e = tid + 256 * k;
+        offA[k] = e < nA ? map_apply(maps[SM_EA], e) : 0;
+        offC[k] = e < nC ? map_apply(maps[SM_EC], e) : 0;
+    }
+    const int eR = tid < nR ? (int)map_apply(maps[SM_RE], tid) : 0;
+    const int eR2 = tid < nR ? (int)map_apply(maps[SM_RE2], tid) : 0;
+    const int64_t bR = tid < nR ? map_apply(maps[SM_RB], tid) : 0;
+    __syncthreads();
+    const int64_t n_tiles = (int64_t)1 << (nr - L);
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int64_t r0 = t << L;
+        const int64_t ab = map_apply(maps[SM_RA], r0), bb = map_apply(maps[SM_RB], r0) + bR,
+                      cb = map_apply(maps[SM_RC], r0);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int e = tid + 256 * k;
+            if (e < nA) TA[swz(e)] = A[ab + offA[k]];
+        }
+        __syncthreads();
+        if (tid < nR) {
+            float2 a[KMAX];
+#pragma unroll
+            for (int y = 0; y < KMAX; y++)
+                if (y < nK) a[y] = TA[swz(eR + tyE[y])];
+#pragma unroll
+            for (int f = 0; f < FMAX; f++) {
+                if (f < nF) {
+                    float2 acc = make_float2(0.f, 0.f);
+                    const float2 *bp = B + bb + tfB[f];
+#pragma unroll
+                    for (int y = 0; y < KMAX; y++)
+                        if (y < nK) cmac(acc, a[y], bp[tyB[y]]);
+                    TC[swz(eR2 + tfE[f])] = acc;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int e = tid + 256 * k;
+            if (e < nC) C[cb + offC[k]] = TC[swz(e)];
+        }
+    }
+}
+
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
                    hipStream_t s) {
+    if (op.tile_l >= 0) {
+        const int64_t tiles = (int64_t)1 << (op.nr - op.tile_l);
+        const dim3 g((unsigned)std::min<int64_t>(tiles, 256 * 8)), t(256);
+        if (op.kc <= 3 && op.nf <= 3)
+            hipLaunchKernelGGL((k_stream_tile<8, 8>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf, op.tile_l);
+        else
+            hipLaunchKernelGGL((k_stream_tile<32, 32>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf, op.tile_l);
+        return;
+    }
     const int lo = op.nr < 8 ? op.nr : 8;
     const int64_t chunks = (int64_t)1 << (op.nr - lo);
     const unsigned blocks = (unsigned)std::min<int64_t>(chunks, 256 * 16);

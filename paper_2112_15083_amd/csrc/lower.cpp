@@ -326,6 +326,32 @@ struct Lowerer {
         op.m[SM_FC] = make_map(fc);
         op.m[SM_YA] = make_map(ay);
         op.m[SM_YB] = make_map(by);
+        // LDS tiling when both the contracted and the new-leg dimensions are short
+        if (op.kc <= 5 && op.nf <= 5) {
+            int L = std::min(op.nr, 11 - std::max(op.kc, op.nf));
+            if (L >= 1) {
+                op.tile_l = L;
+                std::vector<int> PA, PC;
+                for (int i = 0; i < L; i++) PA.push_back(ra[i]), PC.push_back(rcm[i]);
+                for (int v : ay) PA.push_back(v);
+                for (int v : fc) PC.push_back(v);
+                std::sort(PA.begin(), PA.end());
+                std::sort(PC.begin(), PC.end());
+                auto idx = [](const std::vector<int> &P, int pos) {
+                    return (int)(std::lower_bound(P.begin(), P.end(), pos) - P.begin());
+                };
+                std::vector<int> re(L), ye(ay.size()), re2(L), fe(fc.size());
+                for (int i = 0; i < L; i++) re[i] = idx(PA, ra[i]), re2[i] = idx(PC, rcm[i]);
+                for (size_t j = 0; j < ay.size(); j++) ye[j] = idx(PA, ay[j]);
+                for (size_t j = 0; j < fc.size(); j++) fe[j] = idx(PC, fc[j]);
+                op.m[SM_EA] = make_map(PA);
+                op.m[SM_RE] = make_map(re);
+                op.m[SM_YE] = make_map(ye);
+                op.m[SM_EC] = make_map(PC);
+                op.m[SM_RE2] = make_map(re2);
+                op.m[SM_FE] = make_map(fe);
+            }
+        }
         double f = 8.0 * std::exp2((double)(LC.size() + con.size()));
         double by_ = 8.0 * (double)(size_of(a) + size_of(b) + size_of(t));
         prog.streams.push_back(op);

@@ -253,11 +253,14 @@ void plan_finish(PlanCore &p) {
     }
     // default slice groups (values of the looped legs)
     p.groups.clear();
+    p.n_group_range = 0;
     const int nl = (int)p.looped.size();
     if (p.S.empty()) {
-        if (nl > 40) fail(RQC_EPLAN, "too many looped slice legs for a default slice list");
-        for (uint64_t g = 0; g < ((uint64_t)1 << nl); g++) p.groups.push_back(g);
+        if (nl > 62) fail(RQC_EPLAN, "too many looped slice legs");
+        p.n_group_range = (uint64_t)1 << nl; // groups 0 .. 2^nl - 1, not materialised
     } else {
+        if ((double)p.X.size() * std::exp2((double)(nl - (int)p.S.size())) > (double)(1 << 26))
+            fail(RQC_EPLAN, "default partial slice list exceeds 2^26 groups");
         std::vector<int> s_pos(nl, -1); // looped leg -> index in S
         for (int u = 0; u < nl; u++)
             for (size_t t = 0; t < p.S.size(); t++)
@@ -348,7 +351,7 @@ void plan_finish(PlanCore &p) {
     I.n_sliced = (int32_t)p.sliced.size();
     I.n_batched = (int32_t)p.batched.size();
     I.n_partial = (int32_t)p.S.size();
-    I.n_groups = (int64_t)p.groups.size();
+    I.n_groups = p.n_group_range ? (int64_t)p.n_group_range : (int64_t)p.groups.size();
     I.n_slices = I.n_groups << p.batched.size();
     I.n_partial_kept = (int64_t)p.X.size();
     I.fidelity = p.F;

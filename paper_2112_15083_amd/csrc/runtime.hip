@@ -207,13 +207,14 @@ rqc_status guard(F &&f) {
 
 void dump_plan(const rqc_plan &p) {
     const Program &pg = p.prog;
-    std::fprintf(stderr, "plan: %zu fused subtrees (%zu steps, %d LDS elems), %zu ops, arena %lld elems, %zu groups\n",
+    std::fprintf(stderr, "plan: %zu fused subtrees (%zu steps, %d LDS elems), %zu ops, arena %lld elems, %lld groups\n",
                  pg.small_trees.size(), pg.small_steps.size(), pg.small_lds_elems, pg.ops.size(),
-                 (long long)pg.arena_elems, p.groups.size());
+                 (long long)pg.arena_elems, (long long)p.info.n_groups);
     for (const Op &op : pg.ops) {
         if (op.kind == OP_STREAM) {
             const StreamOp &so = pg.streams[op.index];
-            std::fprintf(stderr, "  stream rc=%d kc=%d flops=%.3g bytes=%.3g\n", so.rc, so.kc, op.flops, op.bytes);
+            std::fprintf(stderr, "  stream rc=%d kc=%d nr=%d nf=%d tile=%d flops=%.3g bytes=%.3g\n", so.rc, so.kc,
+                         so.nr, so.nf, so.tile_l, op.flops, op.bytes);
         } else if (op.kind == OP_GEMM) {
             const GemmOp &g = pg.gemms[op.index];
             std::fprintf(stderr, "  gemm b=%lld M=%lld N=%lld K=%lld ak=%d bn=%d flops=%.3g\n", (long long)g.batch,
@@ -227,8 +228,23 @@ void dump_plan(const rqc_plan &p) {
 }
 
 // Run the plan's program for every (batch, slice group) pair.
-void execute(rqc_plan *p, const std::vector<uint64_t> &groups, const uint64_t *fixed_bits, int64_t n_batches,
-             void *out_amps, void *out_f64, hipStream_t s) {
+// Slice groups to run: an explicit list of looped-leg values, or 0 .. range-1.
+struct GroupList {
+    const std::vector<uint64_t> *list = nullptr;
+    uint64_t range = 0;
+    uint64_t size() const { return list ? list->size() : range; }
+    uint64_t operator[](uint64_t i) const { return list ? (*list)[i] : i; }
+};
+
+GroupList default_groups(const rqc_plan *p) {
+    GroupList g;
+    if (p->n_group_range) g.range = p->n_group_range;
+    else g.list = &p->groups;
+    return g;
+}
+
+void execute(rqc_plan *p, const GroupList &groups, const uint64_t *fixed_bits, int64_t n_batches, void *out_amps,
+             void *out_f64, hipStream_t s) {
     const Program &pg = p->prog;
     const int n_open = (int)p->spec.open_vars.size();
     const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
@@ -241,7 +257,8 @@ void execute(rqc_plan *p, const std::vector<uint64_t> &groups, const uint64_t *f
             Timer t(p, s, RQC_K_ACCUM, 0, 16.0 * nout);
             launch_zero(p->d_acc, nout, s);
         }
-        for (uint64_t g : groups) {
+        for (uint64_t gi = 0; gi < groups.size(); gi++) {
+            const uint64_t g = groups[gi];
             ProjVals vals{};
             for (int i = 0; i < nfix; i++)
                 if ((fixed_bits[bi] >> p->spec.fixed_bit[i]) & 1) vals.w[i >> 6] |= 1ull << (i & 63);
@@ -341,7 +358,7 @@ std::vector<double> gpu_norms(const rqc_plan_opts &outer, const NetSpec &spec, c
     std::vector<double2> host(n);
     try {
         uint64_t zero = 0;
-        execute(&q, q.groups, &zero, 1, amps, r64, nullptr);
+        execute(&q, default_groups(&q), &zero, 1, amps, r64, nullptr);
         HIP_OK(hipMemcpy(host.data(), r64, n * sizeof(double2), hipMemcpyDeviceToHost));
     } catch (...) {
         (void)hipFree(amps);
@@ -486,7 +503,7 @@ rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64
         if (dev != p->device) fail(RQC_EDEVICE, "plan belongs to another device");
         const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
         if (!slice_ids) {
-            execute(p, p->groups, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
+            execute(p, default_groups(p), fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
             return;
         }
         if (n_slices < 0) fail(RQC_EINVAL, "negative slice count");
@@ -513,7 +530,9 @@ rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64
             groups.push_back(kv[i].first);
             i = j;
         }
-        execute(p, groups, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
+        GroupList gl;
+        gl.list = &groups;
+        execute(p, gl, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
     });
 }
 
