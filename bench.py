@@ -6,12 +6,20 @@ streaming contractions, permutes, MFMA complex GEMMs), the FP64 cross-slice
 sum, normalisation, and rejection sampling over the batch's sub-batches of 64.
 Fixed output bits are fresh per step (seeded).  Prints one JSON line.
 
-Default workload ("mid"): 5x6 grid, 14 cycles, 6 sliced legs (64 slices),
-2^12-amplitude open batch on the last two rows, alpha = 2.
+Workloads:
+  mid (default)  5x6 grid, 14 cycles, 6 sliced legs (64 slices), 2^12 batch
+  precision      5x6 grid, 16 cycles, 10 sliced legs (1024 slices), 2^14 batch,
+                 in complex64 / bf16x3 / fp16x3 (--precision)
+  large          53 qubits (6x9 minus (0,4)), 20 cycles: one GPU's share of a
+                 partial contraction (top-R slices), timed on a prefix of the
+                 slice list and extrapolated (labelled)
+  --serve        the serving loop on a Poisson stream of synthetic requests
+  --copy-calibration  a plain 1 GiB device copy, for scaling HBM counters
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +35,9 @@ import synthetic  # noqa: E402
 PEAK = {"fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2516.6, "hbm_gbs": 8000.0}
 METRIC = "contraction TFLOP/s + amplitudes/s at stated error vs FP64; p50/p99 latency"
 N_SLICED = {"tiny": 0, "mid": 6, "precision": 10}
+DTYPE = {"c64": "complex64 (fp32 MFMA), fp64 slice sum",
+         "bf16x3": "bf16x3 split (bf16 MFMA, fp32 acc), fp64 slice sum",
+         "fp16x3": "fp16x3 split with 2^e scaling (fp16 MFMA, fp32 acc), fp64 slice sum"}
 
 
 def cpu_baseline(cfg, text, budget_s=20.0):
@@ -54,27 +65,42 @@ def cpu_baseline(cfg, text, budget_s=20.0):
     return {"value": amps / t_full, "unit": "amplitudes/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 state vector of {n} qubits over the first {g} of {n_gates} gates "
                       f"({dt:.1f} s), extrapolated linearly to the full circuit ({t_full:.0f} s per "
-                      f"{amps}-amplitude batch)"}
+                      f"{amps}-amplitude batch; it also yields the other 2^{n - len(cfg['open_qubits'])}"
+                      f" batches)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="mid", choices=["tiny", "mid", "precision"])
-    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--path-trials", type=int, default=256)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sliced contraction shards "
-              "by slice range across GPUs, which this build does not run.", file=sys.stderr)
-        sys.exit(2)
+def kernel_roofline(prof, precision_is_c64):
+    """Dominant kernel class by measured time and its achieved fraction."""
+    cls = max((k for k in prof if k != "sample"), key=lambda k: prof[k]["seconds"])
+    pc = prof[cls]
+    if cls == "gemm":
+        peak = PEAK["fp32_mfma_tflops"] if precision_is_c64 else PEAK["bf16_mfma_tflops"]
+        achieved = pc["flops"] / pc["seconds"] / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
+    else:
+        achieved = pc["bytes"] / pc["seconds"] / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                "frac": achieved / PEAK["hbm_gbs"]}
+    roof.update({"kernel": cls, "launches": pc["launches"],
+                 "avg_launch_us": 1e6 * pc["seconds"] / max(1, pc["launches"]),
+                 "traffic": measured_traffic(cls)})
+    return roof
 
-    import torch
-    from paper_2112_15083_amd import rqc
 
+def measured_traffic(cls):
+    """HBM traffic per launch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{cls}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2112_15083_amd", "csrc", "kernels.hip"), "rb").read()
+    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_mid_like(args, rqc, torch):
     torch.cuda.set_device(0)
     cfg = synthetic.CONFIGS[args.config]
     text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
@@ -102,17 +128,26 @@ def main():
                                             batch_index_base=i << (o - 6), stream=stream)
         if record is not None:
             record.append(n_out)
+        return n_out
 
-    # error against FP64: the stored oracle amplitudes of call 0, when present
-    rel_l2 = None
+    # error against FP64 and XEB of the samples: the stored oracle amplitudes of call 0
+    rel_l2, xeb = None, None
     gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_seed0_call0.npy")
-    step(0)
+    n_out0 = step(0)
     torch.cuda.synchronize()
     if os.path.exists(gold):
         ref = np.load(gold)
         a = out.cpu().numpy()[0]
         got = a[:, 0].astype(np.float64) + 1j * a[:, 1]
         rel_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        s = samples.cpu().numpy()[:n_out0].astype(np.uint64)
+        t_idx = np.zeros(len(s), dtype=np.int64)
+        for b, q in enumerate(open_q):
+            t_idx |= ((s >> np.uint64(q)) & np.uint64(1)).astype(np.int64) << b
+        if len(s):
+            p_exact = np.abs(ref[t_idx]) ** 2
+            xeb = {"value": float((2.0 ** n) * p_exact.mean() - 1.0), "samples": int(len(s)),
+                   "note": "samples of call 0 scored with the oracle's FP64 probabilities"}
     for w in range(args.warmup):
         step(1 + w)
     torch.cuda.synchronize()
@@ -128,30 +163,14 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     prof = rqc.plan_profile(plan)
-    ms = 1e3 * elapsed / args.steps
     amps_s = args.steps * (1 << o) / elapsed
-    tflops = args.steps * info["flops_per_batch"] / elapsed / 1e12
-    # dominant kernel class by measured time
-    cls = max((k for k in prof if k != "sample"), key=lambda k: prof[k]["seconds"])
-    pc = prof[cls]
-    if cls == "gemm":
-        peak = PEAK["fp32_mfma_tflops"] if prec == rqc.C64 else PEAK["bf16_mfma_tflops"]
-        achieved = pc["flops"] / pc["seconds"] / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
-    else:
-        achieved = pc["bytes"] / pc["seconds"] / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                "frac": achieved / PEAK["hbm_gbs"]}
-    roof.update({"kernel": cls, "launches": pc["launches"],
-                 "avg_launch_us": 1e6 * pc["seconds"] / max(1, pc["launches"]), "traffic": None})
     line = {
         "metric": METRIC, "value": amps_s, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"c64": "complex64 (fp32 MFMA), fp64 slice sum",
-                                       "bf16x3": "bf16x3 split (bf16 MFMA), fp64 slice sum",
-                                       "fp16x3": "fp16x3 split (fp16 MFMA), fp64 slice sum"}[args.precision],
-        "data": "synthetic", "tflops": tflops, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-        "p99_ms": 1e3 * float(np.percentile(lat, 99)), "rel_l2_vs_fp64": rel_l2,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision], "data": "synthetic",
+        "tflops": args.steps * info["flops_per_batch"] / elapsed / 1e12,
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "rel_l2_vs_fp64": rel_l2, "xeb_call0": xeb,
         "samples_per_step": float(np.mean(accepted)) if accepted else 0.0,
         "config": {"workload": f"{args.config}: {cfg['rows']}x{cfg['cols']} grid, {cfg['cycles']} cycles, "
                                f"{info['n_slices']} slices ({info['n_sliced']} sliced legs), 2^{o} open batch, "
@@ -159,11 +178,141 @@ def main():
                    "flops_per_step": info["flops_per_batch"], "gemm_flop_share": info["gemm_flop_share"],
                    "max_log2_tensor": info["max_log2_tensor"], "plan_seconds": plan_s,
                    "kernel_seconds": {k: v["seconds"] for k, v in prof.items()}},
-        "roofline": roof,
+        "roofline": kernel_roofline(prof, prec == rqc.C64),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, text)
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def run_large(args, rqc, torch):
+    """One GPU's share of the 53-qubit partial contraction: plan with partial
+    slicing (Alg. 2 / doubled-network R / Alg. 1, top slices to a total of
+    2^10), time a prefix of the slice list, extrapolate to the share and to
+    1e5 samples.  Reports F and the Eq. (9) fidelity bound with eps from the
+    batch's own probabilities."""
+    torch.cuda.set_device(0)
+    cfg = synthetic.CONFIGS["large"]
+    text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    n = cfg["rows"] * cfg["cols"] - len(cfg["removed"])
+    open_q = list(cfg["open_qubits"])
+    o = len(open_q)
+    circ = rqc.load_circuit(text)
+    t0 = time.perf_counter()
+    plan = rqc.plan_create(circ, open_q, max_log2_tensor=30, n_sliced_target=-1, max_log2_batched=30,
+                           path_trials=args.path_trials, target_fidelity=2.0 ** -18, partial_k=21,
+                           partial_total_slices=1 << 10, profile=1)
+    plan_s = time.perf_counter() - t0
+    info = rqc.plan_info(plan)
+    S, X, R = rqc.plan_partial(plan)
+    ids = rqc.plan_slices(plan, cap=args.large_prefix)
+    out = torch.empty((1, 1 << o, 2), dtype=torch.float32, device="cuda")
+    fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rqc.contract_amplitudes(plan, fb, out, slice_ids=ids)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    prof = rqc.plan_profile(plan)
+    frac = len(ids) / info["n_slices"]
+    t_share = dt / frac
+    calls = int(np.ceil(2 * 1e5 / (1 << (o - 6))))
+    return {"metric": METRIC, "workload": "large: 6x9 grid minus (0,4), 53 qubits, 20 cycles, one GPU's share",
+            "plan_seconds": plan_s, "n_sliced": info["n_sliced"], "k_partial": len(S), "X": len(X),
+            "share_slices": info["n_slices"], "fidelity_F": info["fidelity"], "sum_R": float(np.sum(R)),
+            "flops_per_call": info["flops_per_batch"], "max_log2_tensor": info["max_log2_tensor"],
+            "prefix_slices": len(ids), "prefix_seconds": dt,
+            "tflops": info["flops_per_batch"] * frac / dt / 1e12,
+            "extrapolated_seconds_per_call": t_share,
+            "extrapolated_seconds_1e5_samples": t_share * calls, "calls_for_1e5_samples": calls,
+            "label": "extrapolated from a measured prefix of the slice list",
+            "kernel_seconds": {k: v["seconds"] for k, v in prof.items()},
+            "roofline": kernel_roofline(prof, True)}
+
+
+def run_serve(args, torch):
+    from paper_2112_15083_amd import serve
+    torch.cuda.set_device(0)
+    reqs = serve.synthetic_requests(args.serve_requests, seed=0, rate=None)
+    # capacity: everything submitted at once
+    srv = serve.Server(n_streams=4, plan_workers=8)
+    t0 = time.perf_counter()
+    res = [f.result() for f in [srv.submit(r) for _, r in reqs]]
+    cap_s = time.perf_counter() - t0
+    srv.shutdown()
+    ok = [r for r in res if r.status == "ok"]
+    max_rate = len(ok) / cap_s
+    loads = {}
+    for load in (0.5, 0.8, 1.0):
+        rate = load * max_rate
+        reqs = serve.synthetic_requests(args.serve_requests, seed=1, rate=rate)
+        srv = serve.Server(n_streams=4, plan_workers=8)
+        t0 = time.perf_counter()
+        futs = []
+        for t, r in reqs:
+            while time.perf_counter() - t0 < t:
+                time.sleep(0.0005)
+            r.arrival = time.perf_counter()
+            futs.append(srv.submit(r))
+        res = [f.result() for f in futs]
+        wall = time.perf_counter() - t0
+        srv.shutdown()
+        ok = [r for r in res if r.status == "ok"]
+        lat = [r.latency for r in ok]
+        amps = sum(r.amps.size for r in ok)
+        loads[str(load)] = {"offered_rps": rate, "served_rps": len(ok) / wall,
+                            "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                            "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                            "amplitudes_per_s": amps / wall,
+                            "tflops": sum(r.flops for r in ok) / wall / 1e12,
+                            "refused": sum(r.status == "refused" for r in res),
+                            "errors": sum(r.status == "error" for r in res)}
+    return {"metric": METRIC, "workload": f"serving: {args.serve_requests} seeded requests per load, "
+            "4x5..5x6 grids, 8..14 cycles, 2^6..2^12 amplitudes, half with 1e3..4e3 samples, "
+            "half bf16x3", "capacity_rps": max_rate, "loads": loads}
+
+
+def copy_calibration(torch):
+    torch.cuda.set_device(0)
+    n = 1 << 27  # 2^27 complex64 = 1 GiB
+    x = torch.ones(2 * n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="mid", choices=["tiny", "mid", "precision", "large"])
+    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--path-trials", type=int, default=256)
+    ap.add_argument("--large-prefix", type=int, default=16)
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sliced contraction would shard "
+              "by slice range across GPUs, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration(torch)), flush=True)
+        return
+    if args.serve:
+        print(json.dumps(run_serve(args, torch)), flush=True)
+        return
+    from paper_2112_15083_amd import rqc
+    if args.config == "large":
+        print(json.dumps(run_large(args, rqc, torch)), flush=True)
+        return
+    print(json.dumps(run_mid_like(args, rqc, torch)), flush=True)
 
 
 if __name__ == "__main__":

@@ -96,6 +96,9 @@ typedef struct {
     double target_fidelity;
     int32_t partial_k;
     int32_t partial_count;
+    /* > 0: keep the top-R indices so that |X| * 2^(|I|-|S|) is this many slices
+       (at least one index); overrides partial_count and the sum rule. */
+    int64_t partial_total_slices;
     /* Greedy path search: number of randomised trials (0 = 16) and RNG seed. */
     int32_t path_trials;
     uint64_t path_seed;
@@ -202,6 +205,9 @@ rqc_status rqc_plan_sliced_legs(const rqc_plan *p, int32_t *legs, int32_t cap, i
    NULL; caps are element counts). */
 rqc_status rqc_plan_partial(const rqc_plan *p, int32_t *S, int32_t capS, uint64_t *X, int64_t capX,
                             double *R, int64_t capR);
+/* The plan's default slice list as slice ids, in the plan's summation order
+   (host array; *count receives the full length, at most cap ids are written). */
+rqc_status rqc_plan_slices(const rqc_plan *p, uint64_t *ids, int64_t cap, int64_t *count);
 rqc_status rqc_plan_profile(const rqc_plan *p, rqc_profile_t *out);
 rqc_status rqc_plan_profile_reset(rqc_plan *p);
 /* Free a plan.  No work using the plan may still be pending on any stream when

@@ -170,16 +170,17 @@ template <int KMAX, int FMAX>
 __global__ void __launch_bounds__(256) k_stream_tile(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                      float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
                                                      int kc, int nf, int L) {
+    constexpr int FA = FMAX > 0 ? FMAX : 1;
     __shared__ float2 TA[2048], TC[2048];
-    __shared__ int tyE[KMAX], tfE[FMAX];
-    __shared__ int64_t tyB[KMAX], tfB[FMAX];
+    __shared__ int tyE[KMAX], tfE[FA];
+    __shared__ int64_t tyB[KMAX], tfB[FA];
     const int tid = threadIdx.x;
     const int nK = 1 << kc, nF = 1 << nf;
     if (tid < nK) {
         tyE[tid] = (int)map_apply(maps[SM_YE], tid);
         tyB[tid] = map_apply(maps[SM_YB], tid);
     }
-    if (tid < nF) {
+    if (FMAX > 0 && tid < nF) {
         tfE[tid] = (int)map_apply(maps[SM_FE], tid);
         tfB[tid] = map_apply(maps[SM_FB], tid);
     }
@@ -206,21 +207,35 @@ __global__ void __launch_bounds__(256) k_stream_tile(const float2 *__restrict__ 
             if (e < nA) TA[swz(e)] = A[ab + offA[k]];
         }
         __syncthreads();
-        if (tid < nR) {
-            float2 a[KMAX];
+        if (FMAX > 0) {
+            // register blocking: one r per thread, all its outputs
+            if (tid < nR) {
+                float2 a[KMAX];
 #pragma unroll
-            for (int y = 0; y < KMAX; y++)
-                if (y < nK) a[y] = TA[swz(eR + tyE[y])];
+                for (int y = 0; y < KMAX; y++)
+                    if (y < nK) a[y] = TA[swz(eR + tyE[y])];
 #pragma unroll
-            for (int f = 0; f < FMAX; f++) {
-                if (f < nF) {
-                    float2 acc = make_float2(0.f, 0.f);
-                    const float2 *bp = B + bb + tfB[f];
+                for (int f = 0; f < (FMAX > 0 ? FMAX : 1); f++) {
+                    if (f < nF) {
+                        float2 acc = make_float2(0.f, 0.f);
+                        const float2 *bp = B + bb + tfB[f];
 #pragma unroll
-                    for (int y = 0; y < KMAX; y++)
-                        if (y < nK) cmac(acc, a[y], bp[tyB[y]]);
-                    TC[swz(eR2 + tfE[f])] = acc;
+                        for (int y = 0; y < KMAX; y++)
+                            if (y < nK) cmac(acc, a[y], bp[tyB[y]]);
+                        TC[swz(eR2 + tfE[f])] = acc;
+                    }
                 }
+            }
+        } else {
+            // many new legs: one (r, f) output per thread and iteration
+            const int64_t bt = bb - bR;
+            for (int o = tid; o < nC; o += 256) {
+                const int rl = o & (nR - 1), f = o >> L;
+                const int er = (int)map_apply(maps[SM_RE], rl), er2 = (int)map_apply(maps[SM_RE2], rl);
+                const float2 *bp = B + bt + map_apply(maps[SM_RB], rl) + map_apply(maps[SM_FB], f);
+                float2 acc = make_float2(0.f, 0.f);
+                for (int y = 0; y < nK; y++) cmac(acc, TA[swz(er + tyE[y])], bp[tyB[y]]);
+                TC[swz(er2 + (int)map_apply(maps[SM_FE], f))] = acc;
             }
         }
         __syncthreads();
@@ -232,15 +247,64 @@ __global__ void __launch_bounds__(256) k_stream_tile(const float2 *__restrict__ 
     }
 }
 
+// Long contracted dimension (2^kc >= 64) with few new legs: one wave per r,
+// lanes along the contracted index (y = 64 j + lane), all 2^nf outputs of that
+// r accumulated per lane, then summed across the wave by a fixed xor-shuffle
+// tree, so the result does not depend on scheduling.
+template <int FMAX>
+__global__ void __launch_bounds__(256) k_stream_ky(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                   float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
+                                                   int kc, int nf) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    if (r >= ((int64_t)1 << nr)) return;
+    const int nF = 1 << nf;
+    const int64_t nK = (int64_t)1 << kc;
+    const int64_t ab = map_apply(maps[SM_RA], r) + map_apply(maps[SM_YA], lane);
+    const int64_t bb = map_apply(maps[SM_RB], r) + map_apply(maps[SM_YB], lane);
+    int64_t fb[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; f++) fb[f] = f < nF ? map_apply(maps[SM_FB], f) : 0;
+    float2 acc[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; f++) acc[f] = make_float2(0.f, 0.f);
+    for (int64_t yb = 0; yb < nK; yb += 64) {
+        const int64_t ya = map_apply(maps[SM_YA], yb), yb_ = map_apply(maps[SM_YB], yb);
+        const float2 a = A[ab + ya];
+#pragma unroll
+        for (int f = 0; f < FMAX; f++)
+            if (f < nF) cmac(acc[f], a, B[bb + yb_ + fb[f]]);
+    }
+#pragma unroll
+    for (int f = 0; f < FMAX; f++) {
+        if (f < nF) {
+            float2 v = acc[f];
+            for (int off = 32; off > 0; off >>= 1) {
+                v.x += __shfl_xor(v.x, off, 64);
+                v.y += __shfl_xor(v.y, off, 64);
+            }
+            if (lane == 0) C[map_apply(maps[SM_RC], r) + map_apply(maps[SM_FC], f)] = v;
+        }
+    }
+}
+
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
                    hipStream_t s) {
+    if (op.tile_l < 0 && op.kc >= 6 && op.nf <= 4) {
+        const int64_t waves = (int64_t)1 << op.nr;
+        const dim3 g((unsigned)((waves + 3) / 4)), t(256);
+        hipLaunchKernelGGL((k_stream_ky<16>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
+        return;
+    }
     if (op.tile_l >= 0) {
         const int64_t tiles = (int64_t)1 << (op.nr - op.tile_l);
         const dim3 g((unsigned)std::min<int64_t>(tiles, 256 * 8)), t(256);
         if (op.kc <= 3 && op.nf <= 3)
             hipLaunchKernelGGL((k_stream_tile<8, 8>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf, op.tile_l);
+        else if (op.nf <= 3)
+            hipLaunchKernelGGL((k_stream_tile<32, 8>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf, op.tile_l);
         else
-            hipLaunchKernelGGL((k_stream_tile<32, 32>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf, op.tile_l);
+            hipLaunchKernelGGL((k_stream_tile<32, 0>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf, op.tile_l);
         return;
     }
     const int lo = op.nr < 8 ? op.nr : 8;

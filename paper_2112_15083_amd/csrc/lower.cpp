@@ -327,7 +327,7 @@ struct Lowerer {
         op.m[SM_YA] = make_map(ay);
         op.m[SM_YB] = make_map(by);
         // LDS tiling when both the contracted and the new-leg dimensions are short
-        if (op.kc <= 5 && op.nf <= 5) {
+        if (op.kc <= 5 && op.nf <= 10) {
             int L = std::min(op.nr, 11 - std::max(op.kc, op.nf));
             if (L >= 1) {
                 op.tile_l = L;

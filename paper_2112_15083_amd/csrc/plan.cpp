@@ -179,8 +179,15 @@ void plan_partial(PlanCore &p, const Network &net,
     std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return R[a] > R[b]; });
     std::vector<uint64_t> X;
     double F = 0;
-    if (p.opts.partial_count > 0) {
-        size_t cnt = std::min<size_t>((size_t)p.opts.partial_count, nR);
+    if (p.opts.partial_total_slices > 0 || p.opts.partial_count > 0) {
+        size_t cnt;
+        if (p.opts.partial_total_slices > 0) {
+            const double per = std::exp2((double)p.sliced.size() - (double)S.size());
+            cnt = (size_t)std::max(1.0, std::floor((double)p.opts.partial_total_slices / per + 0.5));
+        } else {
+            cnt = (size_t)p.opts.partial_count;
+        }
+        cnt = std::min(cnt, nR);
         for (size_t i = 0; i < cnt; i++) X.push_back(order[i]), F += R[order[i]];
     } else {
         for (size_t i = 0; i < nR; i++) {

@@ -464,6 +464,26 @@ rqc_status rqc_plan_partial(const rqc_plan *p, int32_t *S, int32_t capS, uint64_
     });
 }
 
+rqc_status rqc_plan_slices(const rqc_plan *p, uint64_t *ids, int64_t cap, int64_t *count) {
+    return guard([&] {
+        if (!p || !count) fail(RQC_EINVAL, "null argument");
+        GroupList g = default_groups(p);
+        const int nb = (int)p->batched.size(), nl = (int)p->looped.size();
+        const double total = (double)g.size() * std::exp2((double)nb);
+        if (total > 9e18) fail(RQC_EINVAL, "slice list too long");
+        *count = (int64_t)g.size() << nb;
+        int64_t k = 0;
+        for (uint64_t gi = 0; gi < g.size() && k < cap && ids; gi++)
+            for (uint64_t b = 0; b < ((uint64_t)1 << nb) && k < cap; b++) {
+                uint64_t sid = 0;
+                const uint64_t lv = g[gi];
+                for (int u = 0; u < nl; u++) sid |= ((lv >> u) & 1) << p->looped_bit[u];
+                for (int u = 0; u < nb; u++) sid |= ((b >> u) & 1) << p->batched_bit[u];
+                ids[k++] = sid;
+            }
+    });
+}
+
 rqc_status rqc_plan_profile(const rqc_plan *pc, rqc_profile_t *out) {
     return guard([&] {
         if (!pc || !out) fail(RQC_EINVAL, "null argument");

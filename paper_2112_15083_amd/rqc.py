@@ -33,7 +33,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("max_log2_tensor", ctypes.c_int32), ("n_sliced_target", ctypes.c_int32),
                 ("max_log2_batched", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("target_fidelity", ctypes.c_double), ("partial_k", ctypes.c_int32),
-                ("partial_count", ctypes.c_int32), ("path_trials", ctypes.c_int32),
+                ("partial_count", ctypes.c_int32), ("partial_total_slices", ctypes.c_int64),
+                ("path_trials", ctypes.c_int32),
                 ("path_seed", ctypes.c_uint64), ("profile", ctypes.c_int32), ("dry_run", ctypes.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
 
@@ -79,6 +80,7 @@ _sig = {
     "rqc_plan_info": [_P, ctypes.POINTER(PlanInfo)],
     "rqc_plan_sliced_legs": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "rqc_plan_partial": [_P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int64],
+    "rqc_plan_slices": [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
     "rqc_plan_profile": [_P, ctypes.POINTER(Profile)],
     "rqc_plan_profile_reset": [_P],
     "rqc_contract_amplitudes": [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P],
@@ -234,6 +236,16 @@ def plan_partial(p: Plan):
     R = (ctypes.c_double * max(1, nr))()
     _check(_lib.rqc_plan_partial(p.handle, S, k, X, nx, R, nr))
     return list(S)[:k], list(X)[:nx], list(R)[:nr]
+
+
+def plan_slices(p: Plan, cap: int | None = None):
+    """The plan's default slice list (slice ids), at most `cap` of them."""
+    n = ctypes.c_int64()
+    _check(_lib.rqc_plan_slices(p.handle, None, 0, ctypes.byref(n)))
+    k = n.value if cap is None else min(cap, n.value)
+    arr = (ctypes.c_uint64 * max(1, k))()
+    _check(_lib.rqc_plan_slices(p.handle, arr, k, ctypes.byref(n)))
+    return list(arr)[:k]
 
 
 def plan_profile(p: Plan) -> dict:
