@@ -418,7 +418,11 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t ntn = g.N / BN, ntm = g.M / BM;
-    const int64_t bid = blockIdx.x;
+    // workgroups go round-robin over the 8 XCDs; give each XCD a contiguous
+    // run of tiles (tiles adjacent in n share an A panel in that XCD's L2)
+    const int64_t nblk = gridDim.x;
+    const int64_t bid = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
+                                         : (int64_t)blockIdx.x;
     const int64_t bz = bid / (ntn * ntm);
     const int64_t m0 = ((bid / ntn) % ntm) * BM, n0 = (bid % ntn) * BN;
     const float2 *A = g.A + bz * g.sa;
@@ -577,7 +581,11 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t ntn = g.N / BN, ntm = g.M / BM;
-    const int64_t bid = blockIdx.x;
+    // workgroups go round-robin over the 8 XCDs; give each XCD a contiguous
+    // run of tiles (tiles adjacent in n share an A panel in that XCD's L2)
+    const int64_t nblk = gridDim.x;
+    const int64_t bid = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
+                                         : (int64_t)blockIdx.x;
     const int64_t bz = bid / (ntn * ntm);
     const int64_t m0 = ((bid / ntn) % ntm) * BM, n0 = (bid % ntn) * BN;
     const float2 *A = g.A + bz * g.sa;

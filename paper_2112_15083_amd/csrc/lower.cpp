@@ -296,6 +296,33 @@ struct Lowerer {
             }
         }
         for (; nb < newb.size(); nb++) LC.push_back(newb[nb]);
+        // If the consumer is a GEMM, write the result directly in that GEMM's
+        // canonical operand layout (A: [K | M | batch], B: [N | K | batch], legs
+        // ascending within groups) so it needs no permute.
+        const int par = parent[t];
+        if (par >= 0 && gemm_worthy(par)) {
+            auto [pa, pb] = tree.steps[par - tree.n_leaves];
+            const Legs &PA = legs[pa], &PB = legs[pb], &PC = legs[par];
+            Legs bt, cn, fa_, fb_;
+            for (int v : PA) {
+                bool inb = contains(PB, v), inc = contains(PC, v);
+                if (inb && inc) bt.push_back(v);
+                else if (inb) cn.push_back(v);
+                else fa_.push_back(v);
+            }
+            for (int v : PB)
+                if (!contains(PA, v)) fb_.push_back(v);
+            std::vector<int> want;
+            if (t == pa) {
+                want = cn;
+                want.insert(want.end(), fa_.begin(), fa_.end());
+            } else {
+                want = fb_;
+                want.insert(want.end(), cn.begin(), cn.end());
+            }
+            want.insert(want.end(), bt.begin(), bt.end());
+            if (set_of(want) == C) LC = want;
+        }
         layout[t] = LC;
         StreamOp op;
         op.a = buf_of(a);

@@ -428,9 +428,9 @@ Tree reconfigure_tree(const Tree &t, const std::vector<Legs> &leaf_legs, int n_v
     return out;
 }
 
-SearchResult search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
-                         const std::vector<char> &forbidden, const std::vector<int> *user_sliced,
-                         int max_log2_tensor, int n_target, int trials, uint64_t seed) {
+std::vector<SearchResult> search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
+                                      const std::vector<char> &forbidden, const std::vector<int> *user_sliced,
+                                      int max_log2_tensor, int n_target, int trials, uint64_t seed) {
     std::vector<SearchResult> res(trials);
     std::vector<char> none(n_vars, 0);
     auto run = [&](int tr) {
@@ -456,10 +456,9 @@ SearchResult search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const s
             for (int tr = next++; tr < trials; tr = next++) run(tr);
         });
     for (auto &th : pool) th.join();
-    int best = 0;
-    for (int tr = 1; tr < trials; tr++)
-        if (res[tr].log2cost < res[best].log2cost - 1e-9) best = tr;
-    return res[best];
+    std::stable_sort(res.begin(), res.end(),
+                     [](const SearchResult &a, const SearchResult &b) { return a.log2cost < b.log2cost; });
+    return res;
 }
 
 std::vector<int> greedy_slice(const Tree &t, const std::vector<Legs> &legs, int n_vars,
