@@ -253,7 +253,8 @@ def run_large(args, rqc, torch):
 def run_serve(args, torch):
     from paper_2112_15083_amd import serve
     torch.cuda.set_device(0)
-    reqs = serve.synthetic_requests(args.serve_requests, seed=0, rate=None)
+    kw = dict(shapes=((4, 5), (4, 6), (5, 5), (5, 6)), cycles=(8, 12), log2_amps=(6, 12), samples=(100, 400))
+    reqs = serve.synthetic_requests(args.serve_requests, seed=0, rate=None, **kw)
     # capacity: everything submitted at once
     srv = serve.Server(n_streams=4, plan_workers=8)
     t0 = time.perf_counter()
@@ -265,7 +266,7 @@ def run_serve(args, torch):
     loads = {}
     for load in (0.5, 0.8, 1.0):
         rate = load * max_rate
-        reqs = serve.synthetic_requests(args.serve_requests, seed=1, rate=rate)
+        reqs = serve.synthetic_requests(args.serve_requests, seed=1, rate=rate, **kw)
         srv = serve.Server(n_streams=4, plan_workers=8)
         t0 = time.perf_counter()
         futs = []

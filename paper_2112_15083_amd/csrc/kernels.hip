@@ -297,6 +297,8 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
         return;
     }
     if (op.tile_l >= 0) {
+        if (op.tile_l > 8 || op.tile_l + op.kc > 11 || op.tile_l + op.nf > 11 || op.kc > 5)
+            fail(RQC_EPLAN, "streaming tile exceeds the kernel's limits");
         const int64_t tiles = (int64_t)1 << (op.nr - op.tile_l);
         const dim3 g((unsigned)std::min<int64_t>(tiles, 256 * 8)), t(256);
         if (op.kc <= 3 && op.nf <= 3)

@@ -355,7 +355,9 @@ struct Lowerer {
         op.m[SM_YB] = make_map(by);
         // LDS tiling when both the contracted and the new-leg dimensions are short
         if (op.kc <= 5 && op.nf <= 10) {
-            int L = std::min(op.nr, 11 - std::max(op.kc, op.nf));
+            // tiles hold at most 2^11 elements of A and of C, and at most 256
+            // rows (one per thread of the register-blocked form)
+            int L = std::min({op.nr, 11 - std::max(op.kc, op.nf), 8});
             if (L >= 1) {
                 op.tile_l = L;
                 std::vector<int> PA, PC;

@@ -262,7 +262,8 @@ def synthetic_requests(n: int, seed: int = 0, shapes=((4, 5), (4, 6), (5, 5), (5
         u = min(u, nq)
         open_q = list(range(nq - u, nq))
         text = synthetic.circuit_text(r, c, m, 10_000 + rid)
-        ns = int(rng.integers(samples[0], samples[1] + 1)) if rng.random() < sample_frac and u >= 6 else 0
+        # sampling requests use batches of at least 2^10 amplitudes (16 sub-batches)
+        ns = int(rng.integers(samples[0], samples[1] + 1)) if rng.random() < sample_frac and u >= 10 else 0
         n_batches = 1 if ns == 0 else max(1, math.ceil(2.0 * ns / (1 << (u - 6))))
         fixed = synthetic.fixed_bits_batch(nq, open_q, 20_000 + 1000 * rid, n_batches)
         prec = 1 if rng.random() < bf16_frac else 0
