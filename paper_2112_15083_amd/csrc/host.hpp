@@ -111,11 +111,16 @@ std::vector<int> sliced_vertex_select(const LightCones &lc, const std::vector<in
 enum OpKind { OP_SMALL = 0, OP_STREAM = 1, OP_PERMUTE = 2, OP_GEMM = 3 };
 
 // Bit map from a logical index to an element offset: sum over runs of
-// ((x >> src) & (2^len - 1)) << dst.
+// ((x >> src) & (2^len - 1)) << dst.  Runs are packed in 32-bit words
+// (src | len << 8 | dst << 16) so that device code reads a map with scalar
+// loads when the map is the same for the whole wave.
 constexpr int kMaxRuns = 24;
 struct BitMap {
-    uint8_t n = 0;
-    uint8_t src[kMaxRuns], len[kMaxRuns], dst[kMaxRuns];
+    int32_t n = 0;
+    uint32_t run[kMaxRuns] = {};
+    int src(int i) const { return (int)(run[i] & 255u); }
+    int len(int i) const { return (int)((run[i] >> 8) & 255u); }
+    int dst(int i) const { return (int)(run[i] >> 16); }
 };
 BitMap make_map(const std::vector<int> &logical_to_mem); // entry = memory bit of logical bit, -1 = absent
 
@@ -143,11 +148,28 @@ struct SmallTree {
 // ascending order), staged through LDS: A offset = rA(r0) + EA(e), tile slot of
 // (r, y) = RE(r_low) + YE(y); outputs likewise with C offset = rC(r0) + EC(e'),
 // slot of (r, f) = RE2(r_low) + FE(f).
-enum { SM_RA = 0, SM_RB, SM_RC, SM_FB, SM_FC, SM_YA, SM_YB, SM_EA, SM_RE, SM_YE, SM_EC, SM_RE2, SM_FE, SM_COUNT };
+// Matrix-core form (mx): the same tiles, staged row-major instead: tile element
+// e holds row ER(e) and contracted index EY(e) (A side), or row ER2(e) and new
+// index EF(e) (C side).  The tile's batch legs (r bits that also index B) are
+// its top row bits, so all rows of a quarter tile share one B matrix.
+// Long form (lk, 2^kc >= 64): a workgroup takes 64 rows (the first six r bits,
+// none of them batch legs) and a range of 32-wide chunks of the contracted
+// index (its first five bits); A chunks are staged like tiles (EA / ER / EY),
+// B chunks through EB (element -> B offset), BY and BF (element -> y, f).
+// Chunk ranges (2^lk_split of them) write partial sums to a scratch buffer w
+// laid out [split][r][f], summed afterwards in split order.
+enum {
+    SM_RA = 0, SM_RB, SM_RC, SM_FB, SM_FC, SM_YA, SM_YB, SM_EA, SM_RE, SM_YE, SM_EC, SM_RE2, SM_FE,
+    SM_ER, SM_EY, SM_ER2, SM_EF, SM_EB, SM_BY, SM_BF, SM_COUNT
+};
 struct StreamOp {
     Buf a, b, c;
+    Buf w;           // lk: partial sums
     int rc, kc, nr, nf;
     int tile_l = -1; // >= 0: tiled kernel with 2^tile_l r per tile
+    int mx = 0;      // 1: matrix-core tiled kernel
+    int lk = 0;      // 1: matrix-core long-contraction kernel
+    int lk_split = 0;
     BitMap m[SM_COUNT];
 };
 

@@ -10,13 +10,20 @@
 //   k_finalize      1/sqrt(F) normalisation and complex64 output (Sec. I.C, step 2)
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "kernels.hpp"
 
 namespace rqc {
 
 __device__ __forceinline__ int64_t map_apply(const BitMap &m, int64_t x) {
     int64_t r = 0;
-    for (int i = 0; i < m.n; i++) r |= ((x >> m.src[i]) & ((1LL << m.len[i]) - 1)) << m.dst[i];
+    for (int i = 0; i < m.n; i++) {
+        const uint32_t w = m.run[i];
+        r |= ((x >> (w & 255u)) & ((1LL << ((w >> 8) & 255u)) - 1)) << (w >> 16);
+    }
     return r;
 }
 
@@ -288,8 +295,303 @@ __global__ void __launch_bounds__(256) k_stream_ky(const float2 *__restrict__ A,
     }
 }
 
+// Short contraction on matrix cores.  Per tile of R = 2^L rows (64..256):
+// C[r][f] = sum_y A[r][y] B_r[y][f] with K = 2^KC <= 32 and F = 2^nf <= 32.
+// As a real product, [A_re | A_im] interleaved per y (row length 2K) times the
+// 2K x 2F block matrix with entries B'[2y+c][2f+d] = (B_re, B_im; -B_im, B_re)
+// [c][d] gives C interleaved per f, i.e. the complex rows of C.  Each wave owns
+// a quarter of the tile's rows in 16-row blocks and runs them through
+// v_mfma_f32_16x16x4f32 with B' held in registers (NC blocks of 16 columns);
+// the tile's batch legs are its top two row bits, so a wave's rows share one
+// B matrix.  A and C go through LDS row-major ([row][y] with row stride K+1,
+// [row][f] with stride F+1) between coalesced HBM reads and writes; the next
+// tile's A is loaded into registers while the current one is computed.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int KC, int NC>
+__global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                   float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
+                                                   int nf, int L) {
+    constexpr int K = 1 << KC, KP = K + 1;
+    constexpr int NT = K >= 2 ? K / 2 : 1; // 4-deep real k steps: 2K / 4
+    extern __shared__ float2 lds[];
+    const int R = 1 << L, F = 1 << nf, FP = F + 1;
+    float2 *TA = lds;
+    float2 *TC = lds + R * KP;
+    float *TCf = reinterpret_cast<float *>(TC);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nA = R << KC, nC = R << nf;
+    // Every thread moves 8 elements each way; beyond a tile's size the indices
+    // wrap, so the extra copies read and write identical values.  All tile
+    // loads and stores are thus unconditional, which lets the compiler wait
+    // for exactly the loads it needs instead of for every store in flight.
+    int offA[8], sA[8], offC[8], sC[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int ea = (tid + 256 * k) & (nA - 1), ec = (tid + 256 * k) & (nC - 1);
+        offA[k] = (int)map_apply(maps[SM_EA], ea);
+        sA[k] = (int)map_apply(maps[SM_ER], ea) * KP + (int)map_apply(maps[SM_EY], ea);
+        offC[k] = (int)map_apply(maps[SM_EC], ec);
+        sC[k] = (int)map_apply(maps[SM_ER2], ec) * FP + (int)map_apply(maps[SM_EF], ec);
+    }
+    // MFMA lane roles: A operand row `col`, k = 4t + g; B operand k = 4t + g,
+    // column `col`; result rows 4g + v, column `col`
+    const int g = lane >> 4, col = lane & 15, cpart = g & 1;
+    const int wrow0 = wave * (R >> 2), rbw = R >> 6;
+    float bq[NT][NC];
+    int64_t bcur = -1;
+    const int64_t n_tiles = (int64_t)1 << (nr - L);
+    int64_t t = blockIdx.x;
+    if (t >= n_tiles) return; // whole workgroup
+    float2 pa[8];
+    {
+        const int64_t ab = map_apply(maps[SM_RA], t << L);
+#pragma unroll
+        for (int k = 0; k < 8; k++) pa[k] = A[ab + offA[k]];
+    }
+    // One tile: stage the prefetched A, load the next tile's A, multiply,
+    // store C.  The first tile is peeled off the loop so that every entry to
+    // the loop has the same loads and stores in flight (the next A, then the
+    // previous C), and the wait before staging covers only the loads.
+    auto tile = [&](int64_t t) {
+        const int64_t r0 = t << L;
+#pragma unroll
+        for (int k = 0; k < 8; k++) TA[sA[k]] = pa[k];
+        // the B matrix of this wave's rows, as the lane's entries of B'
+        const int64_t bb = map_apply(maps[SM_RB], r0 + wrow0);
+        if (bb != bcur) {
+            bcur = bb;
+#pragma unroll
+            for (int s = 0; s < NT; s++) {
+                const int y = 2 * s + (g >> 1);
+#pragma unroll
+                for (int cb = 0; cb < NC; cb++) {
+                    const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
+                    float v = 0.f;
+                    if (y < K && f < F) {
+                        const float2 x = B[bb + map_apply(maps[SM_YB], y) + map_apply(maps[SM_FB], f)];
+                        v = d == cpart ? x.x : (cpart ? -x.y : x.y);
+                    }
+                    bq[s][cb] = v;
+                }
+            }
+            // settle these loads here, so that no later wait has to cover them
+            __builtin_amdgcn_s_waitcnt(0x0f70); // vmcnt(0)
+        }
+        __syncthreads();
+        {
+            // next tile's A (the current one again after the last tile)
+            const int64_t tn = t + gridDim.x < n_tiles ? t + gridDim.x : t;
+            const int64_t ab = map_apply(maps[SM_RA], tn << L);
+#pragma unroll
+            for (int k = 0; k < 8; k++) pa[k] = A[ab + offA[k]];
+        }
+        for (int q = 0; q < rbw; q++) {
+            const int rb = wrow0 + 16 * q;
+            floatx4 acc[NC];
+#pragma unroll
+            for (int cb = 0; cb < NC; cb++) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const float2 *arow = TA + (rb + col) * KP + (g >> 1);
+#pragma unroll
+            for (int s = 0; s < NT; s++) {
+                float a = 0.f;
+                if (K >= 2 || (g >> 1) == 0) {
+                    const float2 x = arow[2 * s];
+                    a = cpart ? x.y : x.x;
+                }
+#pragma unroll
+                for (int cb = 0; cb < NC; cb++)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq[s][cb], acc[cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NC; cb++) {
+                const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
+                if (f < F) {
+#pragma unroll
+                    for (int v = 0; v < 4; v++) TCf[2 * ((rb + 4 * g + v) * FP + f) + d] = acc[cb][v];
+                }
+            }
+        }
+        __syncthreads();
+        const int64_t cbase = map_apply(maps[SM_RC], r0);
+#pragma unroll
+        for (int k = 0; k < 8; k++) C[cbase + offC[k]] = TC[sC[k]];
+    };
+    tile(t);
+    for (t += gridDim.x; t < n_tiles; t += gridDim.x) tile(t);
+}
+
+// Long contraction on matrix cores: the same real block product as
+// k_stream_mx, for 2^kc >= 64.  A workgroup owns 64 rows (16 per wave, one
+// B matrix) and a range of 32-wide chunks of the contracted index; each chunk
+// of A ([64][32], row stride 33) and of B ([32][F], row stride F+1) is staged
+// through LDS while the next one is loaded into registers.  The chunk range's
+// partial sums go to P[split][r][f]; k_stream_lk_sum adds the splits in order.
+template <int NC>
+__global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
+                                                   float2 *__restrict__ P, const BitMap *__restrict__ maps, int nr,
+                                                   int kc, int nf, int ks) {
+    constexpr int KP = 33, NT = 16;
+    __shared__ float2 TA[64 * KP];
+    __shared__ float2 TB[32 * 33];
+    const int F = 1 << nf, FP = F + 1, nBt = 32 << nf;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, col = lane & 15, cpart = g & 1;
+    const int64_t gi = (int64_t)blockIdx.x >> ks;
+    const int sp = blockIdx.x & ((1 << ks) - 1);
+    const int nch = 1 << (kc - 5 - ks), c0 = sp * nch;
+    const int64_t r0 = gi << 6;
+    int offA[8], sA[8], offB[4], sB[4];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int e = tid + 256 * k;
+        offA[k] = (int)map_apply(maps[SM_EA], e);
+        sA[k] = (int)map_apply(maps[SM_ER], e) * KP + (int)map_apply(maps[SM_EY], e);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int e = tid + 256 * k;
+        offB[k] = e < nBt ? (int)map_apply(maps[SM_EB], e) : 0;
+        sB[k] = e < nBt ? (int)map_apply(maps[SM_BY], e) * FP + (int)map_apply(maps[SM_BF], e) : 0;
+    }
+    const int64_t abase = map_apply(maps[SM_RA], r0), bbase = map_apply(maps[SM_RB], r0);
+    float2 pa[8], pb[4];
+    auto load = [&](int ch) {
+        const int64_t ya = abase + map_apply(maps[SM_YA], (int64_t)ch << 5);
+        const int64_t yb = bbase + map_apply(maps[SM_YB], (int64_t)ch << 5);
+#pragma unroll
+        for (int k = 0; k < 8; k++) pa[k] = A[ya + offA[k]];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (tid + 256 * k < nBt) pb[k] = B[yb + offB[k]];
+    };
+    floatx4 acc[NC];
+#pragma unroll
+    for (int cb = 0; cb < NC; cb++) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    load(c0);
+    const float2 *arow = TA + (16 * wave + col) * KP + (g >> 1);
+    for (int ch = c0; ch < c0 + nch; ch++) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) TA[sA[k]] = pa[k];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (tid + 256 * k < nBt) TB[sB[k]] = pb[k];
+        __syncthreads();
+        if (ch + 1 < c0 + nch) load(ch + 1);
+#pragma unroll
+        for (int s = 0; s < NT; s++) {
+            const float2 x = arow[2 * s];
+            const float a = cpart ? x.y : x.x;
+            const int y = 2 * s + (g >> 1);
+#pragma unroll
+            for (int cb = 0; cb < NC; cb++) {
+                const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
+                float v = 0.f;
+                if (f < F) {
+                    const float2 bx = TB[y * FP + f];
+                    v = d == cpart ? bx.x : (cpart ? -bx.y : bx.y);
+                }
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, v, acc[cb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    float *Pf = reinterpret_cast<float *>(P);
+    const int64_t pbase = ((int64_t)sp << (nr + nf)) + ((r0 + 16 * wave + 4 * g) << nf);
+#pragma unroll
+    for (int cb = 0; cb < NC; cb++) {
+        const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
+        if (f < F) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) Pf[2 * (pbase + ((int64_t)v << nf) + f) + d] = acc[cb][v];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_stream_lk_sum(const float2 *__restrict__ P, float2 *__restrict__ C,
+                                                       const BitMap *__restrict__ maps, int nr, int nf, int ks) {
+    const int64_t n = (int64_t)1 << (nr + nf);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float2 s = P[i];
+        for (int j = 1; j < (1 << ks); j++) {
+            const float2 x = P[((int64_t)j << (nr + nf)) + i];
+            s.x += x.x;
+            s.y += x.y;
+        }
+        C[map_apply(maps[SM_RC], i >> nf) + map_apply(maps[SM_FC], i & ((1 << nf) - 1))] = s;
+    }
+}
+
+// Workgroups of `fn` (256 threads, `lds` bytes of dynamic LDS) that the
+// current device holds at once; persistent grids are sized to this so that no
+// workgroup waits for another to finish before it starts.
+static int64_t resident_blocks(const void *fn, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, size_t>, int64_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) fail(RQC_EDEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(dev, fn, lds);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    return cache[key] = (int64_t)per_cu * cus;
+}
+
+template <int KC, int NC>
+void launch_stream_mx_nc(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
+                         hipStream_t s) {
+    const int L = op.tile_l;
+    const size_t lds = sizeof(float2) * (((size_t)1 << L) * ((1 << KC) + 1) + ((size_t)1 << L) * ((1 << op.nf) + 1));
+    const int64_t tiles = (int64_t)1 << (op.nr - L);
+    const int64_t res = resident_blocks(reinterpret_cast<const void *>(&k_stream_mx<KC, NC>), lds);
+    const dim3 g((unsigned)std::min<int64_t>(tiles, res)), t(256);
+    hipLaunchKernelGGL((k_stream_mx<KC, NC>), g, t, lds, s, a, b, c, d_maps, op.nr, op.nf, L);
+}
+
+template <int KC>
+void launch_stream_mx(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
+                      hipStream_t s) {
+    if (op.nf <= 3) launch_stream_mx_nc<KC, 1>(op, d_maps, a, b, c, s);
+    else if (op.nf == 4) launch_stream_mx_nc<KC, 2>(op, d_maps, a, b, c, s);
+    else launch_stream_mx_nc<KC, 4>(op, d_maps, a, b, c, s);
+}
+
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
-                   hipStream_t s) {
+                   float2 *w, hipStream_t s) {
+    if (op.mx) {
+        if (op.tile_l < 6 || op.tile_l > 8 || op.tile_l + op.kc > 11 || op.tile_l + op.nf > 11 || op.kc > 5 ||
+            op.nf > 5 || op.nr < op.tile_l)
+            fail(RQC_EPLAN, "matrix-core streaming tile exceeds the kernel's limits");
+        switch (op.kc) {
+        case 0: launch_stream_mx<0>(op, d_maps, a, b, c, s); break;
+        case 1: launch_stream_mx<1>(op, d_maps, a, b, c, s); break;
+        case 2: launch_stream_mx<2>(op, d_maps, a, b, c, s); break;
+        case 3: launch_stream_mx<3>(op, d_maps, a, b, c, s); break;
+        case 4: launch_stream_mx<4>(op, d_maps, a, b, c, s); break;
+        default: launch_stream_mx<5>(op, d_maps, a, b, c, s); break;
+        }
+        return;
+    }
+    if (op.lk) {
+        if (op.kc < 6 || op.nf > 5 || op.nr < 6 || op.lk_split < 0 || op.lk_split > op.kc - 5 || !w)
+            fail(RQC_EPLAN, "long streaming contraction exceeds the kernel's limits");
+        const int64_t blocks = (int64_t)1 << (op.nr - 6 + op.lk_split);
+        if (blocks > (int64_t)1 << 30) fail(RQC_EPLAN, "long streaming contraction grid too large");
+        const dim3 g((unsigned)blocks), t(256);
+        if (op.nf <= 3)
+            hipLaunchKernelGGL((k_stream_lk<1>), g, t, 0, s, a, b, w, d_maps, op.nr, op.kc, op.nf, op.lk_split);
+        else if (op.nf == 4)
+            hipLaunchKernelGGL((k_stream_lk<2>), g, t, 0, s, a, b, w, d_maps, op.nr, op.kc, op.nf, op.lk_split);
+        else
+            hipLaunchKernelGGL((k_stream_lk<4>), g, t, 0, s, a, b, w, d_maps, op.nr, op.kc, op.nf, op.lk_split);
+        const int64_t n = (int64_t)1 << (op.nr + op.nf);
+        const dim3 g2((unsigned)std::min<int64_t>((n + 255) / 256, 256 * 16));
+        hipLaunchKernelGGL(k_stream_lk_sum, g2, t, 0, s, w, c, d_maps, op.nr, op.nf, op.lk_split);
+        return;
+    }
     if (op.tile_l < 0 && op.kc >= 6 && op.nf <= 4) {
         const int64_t waves = (int64_t)1 << op.nr;
         const dim3 g((unsigned)((waves + 3) / 4)), t(256);

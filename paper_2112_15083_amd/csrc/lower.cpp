@@ -38,9 +38,7 @@ BitMap make_map(const std::vector<int> &l2m) {
         int j = i + 1;
         while (j < n && l2m[j] == l2m[j - 1] + 1) j++;
         if (m.n >= kMaxRuns) fail(RQC_EPLAN, "bit map has too many runs");
-        m.src[m.n] = (uint8_t)i;
-        m.len[m.n] = (uint8_t)(j - i);
-        m.dst[m.n] = (uint8_t)l2m[i];
+        m.run[m.n] = (uint32_t)i | (uint32_t)(j - i) << 8 | (uint32_t)l2m[i] << 16;
         m.n++;
         i = j;
     }
@@ -337,6 +335,48 @@ struct Lowerer {
             (std::find(newb.begin(), newb.end(), LC[j]) != newb.end() ? fpos : rest).push_back((int)j);
         op.nr = (int)rest.size();
         op.nf = (int)fpos.size();
+        // A tile is the first L kept legs (the lowest kept positions of A, so
+        // tile reads are contiguous) with all contracted and new legs.
+        const int L = (op.kc <= 5 && op.nf <= 10) ? std::min({op.nr, 11 - std::max(op.kc, op.nf), 8}) : 0;
+        // Matrix-core form: order the tile's legs non-batch first, so that a
+        // quarter tile (one wave's rows) shares one B matrix, then the other
+        // batch legs, so that a workgroup's successive tiles share one too.
+        auto is_batch = [&](int j) { return pos_in(LB, LC[j]) >= 0; };
+        if (L >= 6 && op.kc <= 5 && op.nf <= 5) {
+            int nbt = 0;
+            for (int i = 0; i < L; i++) nbt += is_batch(rest[i]);
+            if (nbt <= 2) {
+                op.mx = 1;
+                std::vector<int> r2;
+                for (int i = 0; i < L; i++)
+                    if (!is_batch(rest[i])) r2.push_back(rest[i]);
+                for (int i = 0; i < L; i++)
+                    if (is_batch(rest[i])) r2.push_back(rest[i]);
+                for (size_t i = L; i < rest.size(); i++)
+                    if (is_batch(rest[i])) r2.push_back(rest[i]);
+                for (size_t i = L; i < rest.size(); i++)
+                    if (!is_batch(rest[i])) r2.push_back(rest[i]);
+                rest = r2;
+            }
+        }
+        // Long contraction on matrix cores: 64 rows per workgroup from six
+        // non-batch kept legs (lowest A positions first), 32-wide chunks of the
+        // contracted index from its five legs with the lowest A positions.
+        if (L == 0 && op.kc >= 6 && op.nf <= 5) {
+            std::vector<int> nbr;
+            for (int j : rest)
+                if (!is_batch(j)) nbr.push_back(j);
+            if (nbr.size() >= 6) {
+                op.lk = 1;
+                std::stable_sort(nbr.begin(), nbr.end(),
+                                 [&](int x, int y) { return pos_in(LA, LC[x]) < pos_in(LA, LC[y]); });
+                std::vector<int> r2(nbr.begin(), nbr.begin() + 6);
+                for (int j : rest)
+                    if (std::find(r2.begin(), r2.end(), j) == r2.end()) r2.push_back(j);
+                rest = r2;
+                std::stable_sort(con.begin(), con.end(), [&](int x, int y) { return pos_in(LA, x) < pos_in(LA, y); });
+            }
+        }
         std::vector<int> ra(rest.size()), rb(rest.size()), rcm(rest.size()), fb(fpos.size()), fc(fpos.size());
         for (size_t j = 0; j < rest.size(); j++) {
             ra[j] = pos_in(LA, LC[rest[j]]);
@@ -353,33 +393,64 @@ struct Lowerer {
         op.m[SM_FC] = make_map(fc);
         op.m[SM_YA] = make_map(ay);
         op.m[SM_YB] = make_map(by);
-        // LDS tiling when both the contracted and the new-leg dimensions are short
-        if (op.kc <= 5 && op.nf <= 10) {
-            // tiles hold at most 2^11 elements of A and of C, and at most 256
-            // rows (one per thread of the register-blocked form)
-            int L = std::min({op.nr, 11 - std::max(op.kc, op.nf), 8});
-            if (L >= 1) {
-                op.tile_l = L;
-                std::vector<int> PA, PC;
-                for (int i = 0; i < L; i++) PA.push_back(ra[i]), PC.push_back(rcm[i]);
-                for (int v : ay) PA.push_back(v);
-                for (int v : fc) PC.push_back(v);
-                std::sort(PA.begin(), PA.end());
-                std::sort(PC.begin(), PC.end());
-                auto idx = [](const std::vector<int> &P, int pos) {
-                    return (int)(std::lower_bound(P.begin(), P.end(), pos) - P.begin());
-                };
-                std::vector<int> re(L), ye(ay.size()), re2(L), fe(fc.size());
-                for (int i = 0; i < L; i++) re[i] = idx(PA, ra[i]), re2[i] = idx(PC, rcm[i]);
-                for (size_t j = 0; j < ay.size(); j++) ye[j] = idx(PA, ay[j]);
-                for (size_t j = 0; j < fc.size(); j++) fe[j] = idx(PC, fc[j]);
-                op.m[SM_EA] = make_map(PA);
-                op.m[SM_RE] = make_map(re);
-                op.m[SM_YE] = make_map(ye);
-                op.m[SM_EC] = make_map(PC);
-                op.m[SM_RE2] = make_map(re2);
-                op.m[SM_FE] = make_map(fe);
-            }
+        if (op.lk) {
+            std::vector<int> PA, PB;
+            for (int i = 0; i < 6; i++) PA.push_back(ra[i]);
+            for (int j = 0; j < 5; j++) PA.push_back(ay[j]), PB.push_back(by[j]);
+            for (int v : fb) PB.push_back(v);
+            std::sort(PA.begin(), PA.end());
+            std::sort(PB.begin(), PB.end());
+            std::vector<int> er(PA.size(), -1), ey(PA.size(), -1), bY(PB.size(), -1), bF(PB.size(), -1);
+            auto idx = [](const std::vector<int> &P, int pos) {
+                return (int)(std::lower_bound(P.begin(), P.end(), pos) - P.begin());
+            };
+            for (int i = 0; i < 6; i++) er[idx(PA, ra[i])] = i;
+            for (int j = 0; j < 5; j++) ey[idx(PA, ay[j])] = j, bY[idx(PB, by[j])] = j;
+            for (size_t j = 0; j < fb.size(); j++) bF[idx(PB, fb[j])] = (int)j;
+            op.m[SM_EA] = make_map(PA);
+            op.m[SM_ER] = make_map(er);
+            op.m[SM_EY] = make_map(ey);
+            op.m[SM_EB] = make_map(PB);
+            op.m[SM_BY] = make_map(bY);
+            op.m[SM_BF] = make_map(bF);
+            // about 2048 workgroups: 2^(nr-6) row groups times the chunk splits
+            op.lk_split = std::max(0, std::min(op.kc - 5, 11 - (op.nr - 6)));
+            op.w.kind = 0;
+            op.w.off = new_alloc((int64_t)1 << (op.lk_split + op.nr + op.nf), -1);
+        }
+        // LDS tiling when both the contracted and the new-leg dimensions are
+        // short: tiles hold at most 2^11 elements of A and of C, and at most 256
+        // rows (one per thread of the register-blocked form)
+        if (L >= 1) {
+            op.tile_l = L;
+            std::vector<int> PA, PC;
+            for (int i = 0; i < L; i++) PA.push_back(ra[i]), PC.push_back(rcm[i]);
+            for (int v : ay) PA.push_back(v);
+            for (int v : fc) PC.push_back(v);
+            std::sort(PA.begin(), PA.end());
+            std::sort(PC.begin(), PC.end());
+            auto idx = [](const std::vector<int> &P, int pos) {
+                return (int)(std::lower_bound(P.begin(), P.end(), pos) - P.begin());
+            };
+            std::vector<int> re(L), ye(ay.size()), re2(L), fe(fc.size());
+            for (int i = 0; i < L; i++) re[i] = idx(PA, ra[i]), re2[i] = idx(PC, rcm[i]);
+            for (size_t j = 0; j < ay.size(); j++) ye[j] = idx(PA, ay[j]);
+            for (size_t j = 0; j < fc.size(); j++) fe[j] = idx(PC, fc[j]);
+            op.m[SM_EA] = make_map(PA);
+            op.m[SM_RE] = make_map(re);
+            op.m[SM_YE] = make_map(ye);
+            op.m[SM_EC] = make_map(PC);
+            op.m[SM_RE2] = make_map(re2);
+            op.m[SM_FE] = make_map(fe);
+            // row-major staging for the matrix-core form: tile element -> row / index
+            std::vector<int> er(PA.size(), -1), ey(PA.size(), -1), er2(PC.size(), -1), ef(PC.size(), -1);
+            for (int i = 0; i < L; i++) er[re[i]] = i, er2[re2[i]] = i;
+            for (size_t j = 0; j < ay.size(); j++) ey[ye[j]] = (int)j;
+            for (size_t j = 0; j < fc.size(); j++) ef[fe[j]] = (int)j;
+            op.m[SM_ER] = make_map(er);
+            op.m[SM_EY] = make_map(ey);
+            op.m[SM_ER2] = make_map(er2);
+            op.m[SM_EF] = make_map(ef);
         }
         double f = 8.0 * std::exp2((double)(LC.size() + con.size()));
         double by_ = 8.0 * (double)(size_of(a) + size_of(b) + size_of(t));
@@ -620,7 +691,10 @@ struct Lowerer {
         };
         for (auto &s : prog.small_steps)
             if (s.c_kind == 2) s.c_off = allocs[s.c_off].off;
-        for (auto &s : prog.streams) fix(s.a), fix(s.b), fix(s.c);
+        for (auto &s : prog.streams) {
+            fix(s.a), fix(s.b), fix(s.c);
+            if (s.lk) fix(s.w);
+        }
         for (auto &p : prog.permutes) fix(p.src), fix(p.dst);
         for (auto &g : prog.gemms) fix(g.a), fix(g.b), fix(g.c);
         for (int t = 0; t < nt; t++)

@@ -213,8 +213,17 @@ void dump_plan(const rqc_plan &p) {
     for (const Op &op : pg.ops) {
         if (op.kind == OP_STREAM) {
             const StreamOp &so = pg.streams[op.index];
-            std::fprintf(stderr, "  stream rc=%d kc=%d nr=%d nf=%d tile=%d flops=%.3g bytes=%.3g\n", so.rc, so.kc,
-                         so.nr, so.nf, so.tile_l, op.flops, op.bytes);
+            // batch legs: r bits that also index B (all of them, and those in a tile)
+            int nbat = 0, nbat_tile = 0;
+            const BitMap &rb = so.m[SM_RB];
+            for (int i = 0; i < rb.n; i++) {
+                nbat += rb.len(i);
+                const int lo = rb.src(i), hi = rb.src(i) + rb.len(i), L = so.tile_l < 0 ? 0 : so.tile_l;
+                nbat_tile += std::max(0, std::min(hi, L) - lo);
+            }
+            std::fprintf(stderr, "  stream %s rc=%d kc=%d nr=%d nf=%d tile=%d batch=%d/%d flops=%.3g bytes=%.3g\n",
+                         so.mx ? "mx" : (so.lk ? "lk" : "vec"), so.rc, so.kc, so.nr, so.nf, so.tile_l, nbat_tile, nbat,
+                         op.flops, op.bytes);
         } else if (op.kind == OP_GEMM) {
             const GemmOp &g = pg.gemms[op.index];
             std::fprintf(stderr, "  gemm b=%lld M=%lld N=%lld K=%lld ak=%d bn=%d flops=%.3g\n", (long long)g.batch,
@@ -282,7 +291,8 @@ void execute(rqc_plan *p, const GroupList &groups, const uint64_t *fixed_bits, i
                 case OP_STREAM: {
                     const StreamOp &so = pg.streams[op.index];
                     Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
-                    launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c), s);
+                    launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c),
+                                  so.lk ? ptr(so.w) : nullptr, s);
                     break;
                 }
                 case OP_PERMUTE: {
