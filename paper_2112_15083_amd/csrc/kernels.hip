@@ -307,6 +307,13 @@ __global__ void __launch_bounds__(256) k_stream_ky(const float2 *__restrict__ A,
 // [row][f] with stride F+1) between coalesced HBM reads and writes; the next
 // tile's A is loaded into registers while the current one is computed.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Buffer resource for 16-byte accesses at 32-bit byte offsets from a tile base
+// (raw buffer, no stride, full range).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float2 *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base), (short)0, -1, 0x00020000);
+}
 
 template <int KC, int NC>
 __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A, const float2 *__restrict__ B,
@@ -320,19 +327,23 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
     float2 *TC = lds + R * KP;
     float *TCf = reinterpret_cast<float *>(TC);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nA = R << KC, nC = R << nf;
-    // Every thread moves 8 elements each way; beyond a tile's size the indices
-    // wrap, so the extra copies read and write identical values.  All tile
-    // loads and stores are thus unconditional, which lets the compiler wait
-    // for exactly the loads it needs instead of for every store in flight.
-    int offA[8], sA[8], offC[8], sC[8];
+    // Every thread moves 4 pairs of adjacent elements each way as 16-byte
+    // accesses (tile bit 0 is tensor bit 0) at 32-bit byte offsets from the
+    // tile base; the pair's two LDS slots are packed in one word.  Beyond a
+    // tile's size the pair index wraps, so the extra copies read and write
+    // identical values: all tile loads and stores are unconditional, which
+    // lets the compiler wait for exactly the loads it needs.
+    const int hA = (R << KC) >> 1, hC = (R << nf) >> 1;
+    uint32_t oA[4], sA[4], oC[4], sC[4];
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-        const int ea = (tid + 256 * k) & (nA - 1), ec = (tid + 256 * k) & (nC - 1);
-        offA[k] = (int)map_apply(maps[SM_EA], ea);
-        sA[k] = (int)map_apply(maps[SM_ER], ea) * KP + (int)map_apply(maps[SM_EY], ea);
-        offC[k] = (int)map_apply(maps[SM_EC], ec);
-        sC[k] = (int)map_apply(maps[SM_ER2], ec) * FP + (int)map_apply(maps[SM_EF], ec);
+    for (int k = 0; k < 4; k++) {
+        const int ea = 2 * ((tid + 256 * k) & (hA - 1)), ec = 2 * ((tid + 256 * k) & (hC - 1));
+        oA[k] = (uint32_t)map_apply(maps[SM_EA], ea) * 8u;
+        sA[k] = (uint32_t)(map_apply(maps[SM_ER], ea) * KP + map_apply(maps[SM_EY], ea)) |
+                (uint32_t)(map_apply(maps[SM_ER], ea + 1) * KP + map_apply(maps[SM_EY], ea + 1)) << 16;
+        oC[k] = (uint32_t)map_apply(maps[SM_EC], ec) * 8u;
+        sC[k] = (uint32_t)(map_apply(maps[SM_ER2], ec) * FP + map_apply(maps[SM_EF], ec)) |
+                (uint32_t)(map_apply(maps[SM_ER2], ec + 1) * FP + map_apply(maps[SM_EF], ec + 1)) << 16;
     }
     // MFMA lane roles: A operand row `col`, k = 4t + g; B operand k = 4t + g,
     // column `col`; result rows 4g + v, column `col`
@@ -343,12 +354,13 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
     const int64_t n_tiles = (int64_t)1 << (nr - L);
     int64_t t = blockIdx.x;
     if (t >= n_tiles) return; // whole workgroup
-    float2 pa[8];
-    {
-        const int64_t ab = map_apply(maps[SM_RA], t << L);
+    u32x4 pa[4];
+    auto load = [&](int64_t tt) {
+        const __amdgpu_buffer_rsrc_t r = tile_rsrc(A + map_apply(maps[SM_RA], tt << L));
 #pragma unroll
-        for (int k = 0; k < 8; k++) pa[k] = A[ab + offA[k]];
-    }
+        for (int k = 0; k < 4; k++) pa[k] = __builtin_amdgcn_raw_buffer_load_b128(r, oA[k], 0, 0);
+    };
+    load(t);
     // One tile: stage the prefetched A, load the next tile's A, multiply,
     // store C.  The first tile is peeled off the loop so that every entry to
     // the loop has the same loads and stores in flight (the next A, then the
@@ -356,7 +368,10 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
     auto tile = [&](int64_t t) {
         const int64_t r0 = t << L;
 #pragma unroll
-        for (int k = 0; k < 8; k++) TA[sA[k]] = pa[k];
+        for (int k = 0; k < 4; k++) {
+            TA[sA[k] & 0xffffu] = make_float2(__uint_as_float(pa[k].x), __uint_as_float(pa[k].y));
+            TA[sA[k] >> 16] = make_float2(__uint_as_float(pa[k].z), __uint_as_float(pa[k].w));
+        }
         // the B matrix of this wave's rows, as the lane's entries of B'
         const int64_t bb = map_apply(maps[SM_RB], r0 + wrow0);
         if (bb != bcur) {
@@ -379,13 +394,8 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
             __builtin_amdgcn_s_waitcnt(0x0f70); // vmcnt(0)
         }
         __syncthreads();
-        {
-            // next tile's A (the current one again after the last tile)
-            const int64_t tn = t + gridDim.x < n_tiles ? t + gridDim.x : t;
-            const int64_t ab = map_apply(maps[SM_RA], tn << L);
-#pragma unroll
-            for (int k = 0; k < 8; k++) pa[k] = A[ab + offA[k]];
-        }
+        // next tile's A (the current one again after the last tile)
+        load(t + gridDim.x < n_tiles ? t + gridDim.x : t);
         for (int q = 0; q < rbw; q++) {
             const int rb = wrow0 + 16 * q;
             floatx4 acc[NC];
@@ -413,9 +423,13 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
             }
         }
         __syncthreads();
-        const int64_t cbase = map_apply(maps[SM_RC], r0);
+        const __amdgpu_buffer_rsrc_t w = tile_rsrc(C + map_apply(maps[SM_RC], r0));
 #pragma unroll
-        for (int k = 0; k < 8; k++) C[cbase + offC[k]] = TC[sC[k]];
+        for (int k = 0; k < 4; k++) {
+            const float2 lo = TC[sC[k] & 0xffffu], hi = TC[sC[k] >> 16];
+            const u32x4 v = {__float_as_uint(lo.x), __float_as_uint(lo.y), __float_as_uint(hi.x), __float_as_uint(hi.y)};
+            __builtin_amdgcn_raw_buffer_store_b128(v, w, oC[k], 0, 0);
+        }
     };
     tile(t);
     for (t += gridDim.x; t < n_tiles; t += gridDim.x) tile(t);

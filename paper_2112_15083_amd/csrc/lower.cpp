@@ -335,9 +335,17 @@ struct Lowerer {
             (std::find(newb.begin(), newb.end(), LC[j]) != newb.end() ? fpos : rest).push_back((int)j);
         op.nr = (int)rest.size();
         op.nf = (int)fpos.size();
-        // A tile is the first L kept legs (the lowest kept positions of A, so
-        // tile reads are contiguous) with all contracted and new legs.
+        // A tile is the first L kept legs with all contracted and new legs.  The
+        // kept legs go lowest first by their lower position in A or C, so that a
+        // tile's reads and writes both run over the low positions of their
+        // tensors even when C's layout does not follow A's.
         const int L = (op.kc <= 5 && op.nf <= 10) ? std::min({op.nr, 11 - std::max(op.kc, op.nf), 8}) : 0;
+        if (L > 0) {
+            std::stable_sort(rest.begin(), rest.end(), [&](int x, int y) {
+                const int kx = std::min(pos_in(LA, LC[x]), x), ky = std::min(pos_in(LA, LC[y]), y);
+                return kx != ky ? kx < ky : pos_in(LA, LC[x]) < pos_in(LA, LC[y]);
+            });
+        }
         // Matrix-core form: order the tile's legs non-batch first, so that a
         // quarter tile (one wave's rows) shares one B matrix, then the other
         // batch legs, so that a workgroup's successive tiles share one too.
@@ -451,6 +459,15 @@ struct Lowerer {
             op.m[SM_EY] = make_map(ey);
             op.m[SM_ER2] = make_map(er2);
             op.m[SM_EF] = make_map(ef);
+            // the matrix-core kernel moves pairs of adjacent elements (tile bit 0
+            // must be tensor bit 0) at 32-bit byte offsets from the tile base
+            if (op.mx) {
+                int64_t spanA = 0, spanC = 0;
+                for (int v : PA) spanA += (int64_t)1 << v;
+                for (int v : PC) spanC += (int64_t)1 << v;
+                if (PA[0] != 0 || PC[0] != 0 || spanA >= ((int64_t)1 << 29) || spanC >= ((int64_t)1 << 29))
+                    op.mx = 0;
+            }
         }
         double f = 8.0 * std::exp2((double)(LC.size() + con.size()));
         double by_ = 8.0 * (double)(size_of(a) + size_of(b) + size_of(t));

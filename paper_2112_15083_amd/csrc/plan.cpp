@@ -342,6 +342,7 @@ void plan_finish(PlanCore &p) {
         if (L.legs.size() > 4) fail(RQC_EPLAN, "leaf with more than 4 legs");
         LeafSel d{};
         d.src = full_off;
+        buf_off = (buf_off + 1) & ~(int64_t)1; // 16-byte aligned tensors
         d.dst = buf_off;
         leaf_off[i] = (int)buf_off;
         for (size_t j = 0; j < L.legs.size(); j++) {
