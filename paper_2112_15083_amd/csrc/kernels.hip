@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -737,12 +738,15 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t ntn = g.N / BN, ntm = g.M / BM;
     // workgroups go round-robin over the 8 XCDs; give each XCD a contiguous
-    // run of tiles (tiles adjacent in n share an A panel in that XCD's L2)
+    // run of tiles, so that tiles sharing an operand panel share that XCD's L2
     const int64_t nblk = gridDim.x;
     const int64_t bid = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
                                          : (int64_t)blockIdx.x;
     const int64_t bz = bid / (ntn * ntm);
-    const int64_t m0 = ((bid / ntn) % ntm) * BM, n0 = (bid % ntn) * BN;
+    // consecutive tiles share the larger operand's panel: m runs fastest when
+    // B is the larger operand (N > M), n otherwise
+    const int64_t m0 = (g.m_fast ? bid % ntm : (bid / ntn) % ntm) * BM;
+    const int64_t n0 = (g.m_fast ? (bid / ntm) % ntn : bid % ntn) * BN;
     const float2 *A = g.A + bz * g.sa;
     const float2 *B = g.B + bz * g.sb;
     float2 *C = g.C + bz * g.sc;
@@ -882,30 +886,40 @@ __device__ __forceinline__ int split_exp(float amax) {
     return s < -120 ? -120 : (s > 120 ? 120 : s);
 }
 
+// Pipelined: stages of 8 complex k (16 real k, one MFMA depth) are loaded
+// into registers two stages ahead, split into hi / lo and written to the other
+// of two LDS buffers while the current one feeds the MFMAs (one barrier per
+// stage).  A and B are both staged interleaved (re, im) per k; the two B
+// operands of the real products, (re, -im) and (im, re) pairs, are formed in
+// registers from the staged pairs: a sign flip of the upper half-word, and a
+// half-word swap, of each 32-bit word.
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
 template <int BM, int BN, int A_KFAST, int B_NFAST, bool F16>
 __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned *__restrict__ amax) {
     using E = typename SplitT<F16>::E;
     using V8 = typename SplitT<F16>::V8;
-    constexpr int BK = 16, BK2 = 32, LD = BK2 + 8;
+    constexpr int BK = 8, LD = 2 * BK + 8;
     constexpr int WM = BM / 64, WN = BN / 64;
-    constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
-    __shared__ __attribute__((aligned(16))) E Ah[BM][LD];
-    __shared__ __attribute__((aligned(16))) E Al[BM][LD];
-    __shared__ __attribute__((aligned(16))) E Brh[BN][LD];
-    __shared__ __attribute__((aligned(16))) E Brl[BN][LD];
-    __shared__ __attribute__((aligned(16))) E Bih[BN][LD];
-    __shared__ __attribute__((aligned(16))) E Bil[BN][LD];
+    constexpr int EA = BM * BK / 256, EB = BN * BK / 256; // complex per thread per stage
+    __shared__ __attribute__((aligned(16))) E Ah[2][BM][LD];
+    __shared__ __attribute__((aligned(16))) E Al[2][BM][LD];
+    __shared__ __attribute__((aligned(16))) E Bh[2][BN][LD];
+    __shared__ __attribute__((aligned(16))) E Bl[2][BN][LD];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t ntn = g.N / BN, ntm = g.M / BM;
     // workgroups go round-robin over the 8 XCDs; give each XCD a contiguous
-    // run of tiles (tiles adjacent in n share an A panel in that XCD's L2)
+    // run of tiles, so that tiles sharing an operand panel share that XCD's L2
     const int64_t nblk = gridDim.x;
     const int64_t bid = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
                                          : (int64_t)blockIdx.x;
     const int64_t bz = bid / (ntn * ntm);
-    const int64_t m0 = ((bid / ntn) % ntm) * BM, n0 = (bid % ntn) * BN;
+    // consecutive tiles share the larger operand's panel: m runs fastest when
+    // B is the larger operand (N > M), n otherwise
+    const int64_t m0 = (g.m_fast ? bid % ntm : (bid / ntn) % ntm) * BM;
+    const int64_t n0 = (g.m_fast ? (bid / ntm) % ntn : bid % ntn) * BN;
     const float2 *A = g.A + bz * g.sa;
     const float2 *B = g.B + bz * g.sb;
     float2 *C = g.C + bz * g.sc;
@@ -917,59 +931,48 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
     }
     const float sa = ldexpf(1.f, ea), sb = ldexpf(1.f, eb);
 
+    // per-thread operand chunk: EA (EB) complex values consecutive in memory
     int a_r, a_c, b_r, b_c;
-    if (A_KFAST) { a_r = tid / (BK / EA); a_c = (tid % (BK / EA)) * EA; }
-    else { a_r = tid / (BM / EA); a_c = (tid % (BM / EA)) * EA; }
-    if (B_NFAST) { b_r = tid / (BN / EB); b_c = (tid % (BN / EB)) * EB; }
-    else { b_r = tid / (BK / EB); b_c = (tid % (BK / EB)) * EB; }
+    if (A_KFAST) { a_r = tid / (BK / EA); a_c = (tid % (BK / EA)) * EA; }      // m, k
+    else { a_r = tid / (BM / EA); a_c = (tid % (BM / EA)) * EA; }              // k, m
+    if (B_NFAST) { b_r = tid / (BN / EB); b_c = (tid % (BN / EB)) * EB; }      // k, n
+    else { b_r = tid / (BK / EB); b_c = (tid % (BK / EB)) * EB; }              // n, k
 
-    float2 ra[EA], rb[EB];
-    auto gload = [&](int64_t k0) {
+    float4 ra[2][EA / 2], rb[2][EB / 2];
+    auto gload = [&](int slot, int64_t k0) {
         const float2 *pa = A_KFAST ? A + (m0 + a_r) * K + k0 + a_c : A + (k0 + a_r) * M + m0 + a_c;
         const float2 *pb = B_NFAST ? B + (k0 + b_r) * N + n0 + b_c : B + (n0 + b_r) * K + k0 + b_c;
 #pragma unroll
-        for (int e = 0; e < EA; e += 2) {
-            float4 v = *reinterpret_cast<const float4 *>(pa + e);
-            ra[e] = make_float2(v.x, v.y);
-            ra[e + 1] = make_float2(v.z, v.w);
-        }
+        for (int e = 0; e < EA / 2; e++) ra[slot][e] = *reinterpret_cast<const float4 *>(pa + 2 * e);
 #pragma unroll
-        for (int e = 0; e < EB; e += 2) {
-            float4 v = *reinterpret_cast<const float4 *>(pb + e);
-            rb[e] = make_float2(v.x, v.y);
-            rb[e + 1] = make_float2(v.z, v.w);
-        }
+        for (int e = 0; e < EB / 2; e++) rb[slot][e] = *reinterpret_cast<const float4 *>(pb + 2 * e);
+        // keep the loads here (a prefetch), not next to their use a stage later
+        asm volatile("" ::: "memory");
     };
-    auto split = [&](float x, E &hi, E &lo) {
-        hi = (E)x;
-        lo = (E)(x - (float)hi);
-    };
-    auto sstore = [&]() {
+    auto sstore = [&](int slot, int buf) {
 #pragma unroll
         for (int e = 0; e < EA; e++) {
+            const float4 v = ra[slot][e >> 1];
+            const float re = (e & 1 ? v.z : v.x) * sa, im = (e & 1 ? v.w : v.y) * sa;
+            const E hr = (E)re, hi_ = (E)im;
+            const E lr = (E)(re - (float)hr), li = (E)(im - (float)hi_);
             const int kk = A_KFAST ? a_c + e : a_r, mm = A_KFAST ? a_r : a_c + e;
-            E h0, l0, h1, l1;
-            split(ra[e].x * sa, h0, l0);
-            split(ra[e].y * sa, h1, l1);
-            Ah[mm][2 * kk] = h0;
-            Ah[mm][2 * kk + 1] = h1;
-            Al[mm][2 * kk] = l0;
-            Al[mm][2 * kk + 1] = l1;
+            Ah[buf][mm][2 * kk] = hr;
+            Ah[buf][mm][2 * kk + 1] = hi_;
+            Al[buf][mm][2 * kk] = lr;
+            Al[buf][mm][2 * kk + 1] = li;
         }
 #pragma unroll
         for (int e = 0; e < EB; e++) {
+            const float4 v = rb[slot][e >> 1];
+            const float re = (e & 1 ? v.z : v.x) * sb, im = (e & 1 ? v.w : v.y) * sb;
+            const E hr = (E)re, hi_ = (E)im;
+            const E lr = (E)(re - (float)hr), li = (E)(im - (float)hi_);
             const int kk = B_NFAST ? b_r : b_c + e, nn = B_NFAST ? b_c + e : b_r;
-            E hr, lr, hi_, li;
-            split(rb[e].x * sb, hr, lr);
-            split(rb[e].y * sb, hi_, li);
-            Brh[nn][2 * kk] = hr;
-            Brh[nn][2 * kk + 1] = -hi_;
-            Brl[nn][2 * kk] = lr;
-            Brl[nn][2 * kk + 1] = -li;
-            Bih[nn][2 * kk] = hi_;
-            Bih[nn][2 * kk + 1] = hr;
-            Bil[nn][2 * kk] = li;
-            Bil[nn][2 * kk + 1] = lr;
+            Bh[buf][nn][2 * kk] = hr;
+            Bh[buf][nn][2 * kk + 1] = hi_;
+            Bl[buf][nn][2 * kk] = lr;
+            Bl[buf][nn][2 * kk + 1] = li;
         }
     };
 
@@ -981,43 +984,68 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
 #pragma unroll
             for (int v = 0; v < 16; v++) cre[i][j][v] = 0.f, cim[i][j][v] = 0.f;
 
-    const int nk = (int)(K / BK);
-    gload(0);
-    for (int kt = 0; kt < nk; kt++) {
-        sstore();
-        __syncthreads();
-        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+    const int ko = 8 * (lane >> 5);
+    const u32x4v flip = {0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u};
+    auto compute = [&](int buf) {
+        V8 ah[WM], al[WM], brh[WN], brl[WN], bih[WN], bil[WN];
 #pragma unroll
-        for (int ks = 0; ks < BK2; ks += 16) {
-            const int ko = ks + 8 * (lane >> 5);
-            V8 ah[WM], al[WM], brh[WN], brl[WN], bih[WN], bil[WN];
+        for (int i = 0; i < WM; i++) {
+            const int mm = wm * (BM / 2) + i * 32 + (lane & 31);
+            ah[i] = *reinterpret_cast<const V8 *>(&Ah[buf][mm][ko]);
+            al[i] = *reinterpret_cast<const V8 *>(&Al[buf][mm][ko]);
+        }
 #pragma unroll
-            for (int i = 0; i < WM; i++) {
-                const int mm = wm * (BM / 2) + i * 32 + (lane & 31);
-                ah[i] = *reinterpret_cast<const V8 *>(&Ah[mm][ko]);
-                al[i] = *reinterpret_cast<const V8 *>(&Al[mm][ko]);
-            }
+        for (int j = 0; j < WN; j++) {
+            const int nn = wn * (BN / 2) + j * 32 + (lane & 31);
+            const u32x4v h = __builtin_bit_cast(u32x4v, *reinterpret_cast<const V8 *>(&Bh[buf][nn][ko]));
+            const u32x4v l = __builtin_bit_cast(u32x4v, *reinterpret_cast<const V8 *>(&Bl[buf][nn][ko]));
+            brh[j] = __builtin_bit_cast(V8, h ^ flip);
+            brl[j] = __builtin_bit_cast(V8, l ^ flip);
+            bih[j] = __builtin_bit_cast(V8, (h >> 16) | (h << 16));
+            bil[j] = __builtin_bit_cast(V8, (l >> 16) | (l << 16));
+        }
+#pragma unroll
+        for (int i = 0; i < WM; i++)
 #pragma unroll
             for (int j = 0; j < WN; j++) {
-                const int nn = wn * (BN / 2) + j * 32 + (lane & 31);
-                brh[j] = *reinterpret_cast<const V8 *>(&Brh[nn][ko]);
-                brl[j] = *reinterpret_cast<const V8 *>(&Brl[nn][ko]);
-                bih[j] = *reinterpret_cast<const V8 *>(&Bih[nn][ko]);
-                bil[j] = *reinterpret_cast<const V8 *>(&Bil[nn][ko]);
+                cre[i][j] = SplitT<F16>::mma(ah[i], brh[j], cre[i][j]);
+                cim[i][j] = SplitT<F16>::mma(ah[i], bih[j], cim[i][j]);
             }
 #pragma unroll
-            for (int i = 0; i < WM; i++)
+        for (int i = 0; i < WM; i++)
 #pragma unroll
-                for (int j = 0; j < WN; j++) {
-                    cre[i][j] = SplitT<F16>::mma(ah[i], brh[j], cre[i][j]);
-                    cre[i][j] = SplitT<F16>::mma(ah[i], brl[j], cre[i][j]);
-                    cre[i][j] = SplitT<F16>::mma(al[i], brh[j], cre[i][j]);
-                    cim[i][j] = SplitT<F16>::mma(ah[i], bih[j], cim[i][j]);
-                    cim[i][j] = SplitT<F16>::mma(ah[i], bil[j], cim[i][j]);
-                    cim[i][j] = SplitT<F16>::mma(al[i], bih[j], cim[i][j]);
-                }
-        }
+            for (int j = 0; j < WN; j++) {
+                cre[i][j] = SplitT<F16>::mma(ah[i], brl[j], cre[i][j]);
+                cim[i][j] = SplitT<F16>::mma(ah[i], bil[j], cim[i][j]);
+            }
+#pragma unroll
+        for (int i = 0; i < WM; i++)
+#pragma unroll
+            for (int j = 0; j < WN; j++) {
+                cre[i][j] = SplitT<F16>::mma(al[i], brh[j], cre[i][j]);
+                cim[i][j] = SplitT<F16>::mma(al[i], bih[j], cim[i][j]);
+            }
+    };
+
+    // stage s lives in register slot s & 1 and LDS buffer s & 1; loads past
+    // the last stage re-read it (unused), so that every iteration issues the
+    // same loads and the waits before staging cover exactly one stage
+    const int nk = (int)(K / BK);
+    gload(0, 0);
+    gload(1, (int64_t)std::min(1, nk - 1) * BK);
+    sstore(0, 0);
+    __syncthreads();
+    // two stages per trip, so that register slots are compile-time indices
+    auto stage = [&](auto par, int kt) {
+        constexpr int cur = decltype(par)::value;
+        gload(cur, (int64_t)std::min(kt + 2, nk - 1) * BK); // stage kt is already in LDS
+        compute(cur);
+        if (kt + 1 < nk) sstore(cur ^ 1, cur ^ 1);
         __syncthreads();
+    };
+    for (int kt = 0; kt < nk; kt += 2) {
+        stage(std::integral_constant<int, 0>{}, kt);
+        if (kt + 1 < nk) stage(std::integral_constant<int, 1>{}, kt + 1);
     }
 #pragma unroll
     for (int i = 0; i < WM; i++)
@@ -1081,7 +1109,9 @@ static void gemm_dispatch(const GemmArgs &g, hipStream_t s) {
     else hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 0>), grid, dim3(256), 0, s, g);
 }
 
-void launch_gemm(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s) {
+void launch_gemm(const GemmArgs &g_in, int precision, unsigned *amax, hipStream_t s) {
+    GemmArgs g = g_in;
+    g.m_fast = g.N > g.M;
     // the split kernels stage 16 complex k per step; shorter contractions stay FP32
     if (precision == RQC_BF16X3 && g.K >= 16) return split_gemm<false>(g, amax, s);
     if (precision == RQC_FP16X3 && g.K >= 16) return split_gemm<true>(g, amax, s);

@@ -30,6 +30,7 @@ struct GemmArgs {
     int64_t batch, M, N, K;
     int64_t sa, sb, sc;
     int a_kfast, b_nfast;
+    int m_fast = 0; // tile order: m fastest (set by the launcher)
 };
 
 void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_sel, int n_leaves,

@@ -121,12 +121,14 @@ static std::vector<Legs> leaf_leg_sets(const NetSpec &s, const std::vector<char>
 // and permute bytes at half the HBM peak, a few microseconds per launch.
 double estimate_seconds(const PlanCore &p) {
     const Program &pg = p.prog;
-    const double gemm_rate = p.opts.precision == RQC_C64 ? 0.8 * 157.3e12 : 0.5 * 838.9e12;
+    // measured rates on MI355X: complex64 GEMM ~80% of FP32 MFMA, split GEMM
+    // ~1/3 of its 3-product ceiling, HBM-bound kernels 4.5-5.5 TB/s
+    const double gemm_rate = p.opts.precision == RQC_C64 ? 0.8 * 157.3e12 : 0.33 * 838.9e12;
     double t = 20e-6;
     for (const Op &op : pg.ops) {
-        if (op.kind == OP_GEMM) t += op.flops / gemm_rate + 4e-6;
-        else if (op.kind == OP_SMALL) t += 60e-6;
-        else t += op.bytes / 4e12 + 4e-6;
+        if (op.kind == OP_GEMM) t += std::max(op.flops / gemm_rate, op.bytes / 5.5e12) + 4e-6;
+        else if (op.kind == OP_SMALL) t += 70e-6;
+        else t += op.bytes / 4.5e12 + 4e-6;
     }
     return t * (double)std::max<int64_t>(1, p.info.n_groups);
 }
