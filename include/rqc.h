@@ -111,6 +111,15 @@ typedef struct {
     rqc_alloc_fn alloc;
     rqc_free_fn free;
     void *alloc_ctx;
+    /* 1 = global cache across batches (the multi-batch reuse the paper's
+       introduction relies on): the parts of the contraction that do not depend
+       on the fixed output bits are computed once per slice group, on the first
+       rqc_contract_amplitudes call over the plan's default slice list, and kept
+       in the workspace; every later call contracts only the parts that depend
+       on its fixed bits.  Results are bitwise identical with and without the
+       cache.  Costs rqc_plan_info_t.cache_bytes of workspace (RQC_EPLAN if that
+       exceeds 128 GiB). */
+    int32_t global_cache;
 } rqc_plan_opts;
 
 typedef struct {
@@ -135,6 +144,10 @@ typedef struct {
     int64_t n_groups;          /* slice groups per batch */
     int64_t workspace_bytes;   /* device memory held by the plan */
     double plan_seconds;       /* host time spent planning */
+    int64_t cache_bytes;       /* global cache held (0 without global_cache) */
+    double flops_cached;       /* of flops_per_batch, the part that does not
+                                  depend on the fixed bits (computed once per
+                                  plan when global_cache is set) */
 } rqc_plan_info_t;
 
 typedef struct {

@@ -125,12 +125,12 @@ struct BitMap {
 BitMap make_map(const std::vector<int> &logical_to_mem); // entry = memory bit of logical bit, -1 = absent
 
 struct Buf {      // where a tensor lives
-    int kind = 0; // 0 = arena, 1 = projected-leaf buffer
+    int kind = 0; // 0 = arena, 1 = projected-leaf buffer, 2 = global cache (per slice group)
     int64_t off = 0; // element offset (complex64 elements)
 };
 
 struct SmallStep { // one contraction inside a fused small subtree
-    int a_kind, b_kind, c_kind; // 0 = LDS, 1 = leaf buffer, 2 = arena (root output)
+    int a_kind, b_kind, c_kind; // 0 = LDS, 1 = leaf buffer, 2 = arena, 3 = global cache (root output)
     int64_t a_off, b_off, c_off;
     int rc, kc;                 // log2 |C|, log2 K
     BitMap ax, bx, ay, by;      // C-index -> A/B offsets, K-index -> A/B offsets
@@ -192,6 +192,7 @@ struct Op {
     int kind;
     int index; // into the per-kind arrays
     double flops, bytes;
+    int dep = 1; // output depends on the fixed output bits (0: computed once per slice group when cached)
 };
 
 // Leaf selection: copy a leaf's sub-tensor with its projected legs fixed.
@@ -213,6 +214,12 @@ struct Program {
     std::vector<PermuteOp> permutes;
     std::vector<GemmOp> gemms;
     std::vector<Op> ops; // launch order (OP_SMALL appears once, first)
+    // global cache: subtrees that do not depend on the fixed output bits; their
+    // outputs read by dependent steps live in a per-slice-group cache block
+    bool cache = false;
+    int n_small_indep = 0;   // small subtrees [0, n) do not depend on fixed bits
+    int64_t cache_elems = 0; // per slice group
+    double flops_indep = 0;  // per slice group
     // final tensor
     Buf root;
     BitMap root_open, root_slice; // open-batch index / batched-slice index -> offset

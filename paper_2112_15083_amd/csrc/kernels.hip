@@ -62,14 +62,15 @@ void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_se
 // ------------------------------------------------------------------ small subtrees
 __global__ void __launch_bounds__(256) k_small_trees(const SmallStep *__restrict__ steps,
                                                      const SmallTree *__restrict__ trees,
-                                                     const float2 *__restrict__ leafbuf, float2 *__restrict__ arena) {
+                                                     const float2 *__restrict__ leafbuf, float2 *__restrict__ arena,
+                                                     float2 *__restrict__ cache) {
     extern __shared__ float2 lds[];
     const SmallTree t = trees[blockIdx.x];
     for (int s = t.first_step; s < t.first_step + t.n_steps; s++) {
         const SmallStep &st = steps[s];
         const float2 *A = st.a_kind == 0 ? lds + st.a_off : (st.a_kind == 1 ? leafbuf + st.a_off : arena + st.a_off);
         const float2 *B = st.b_kind == 0 ? lds + st.b_off : (st.b_kind == 1 ? leafbuf + st.b_off : arena + st.b_off);
-        float2 *C = st.c_kind == 0 ? lds + st.c_off : arena + st.c_off;
+        float2 *C = st.c_kind == 0 ? lds + st.c_off : (st.c_kind == 3 ? cache : arena) + st.c_off;
         const int nC = 1 << st.rc, nK = 1 << st.kc;
         for (int x = threadIdx.x; x < nC; x += blockDim.x) {
             const int64_t ax = map_apply(st.ax, x), bx = map_apply(st.bx, x);
@@ -82,10 +83,10 @@ __global__ void __launch_bounds__(256) k_small_trees(const SmallStep *__restrict
 }
 
 void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int n_trees, int lds_elems,
-                        const float2 *leafbuf, float2 *arena, hipStream_t s) {
+                        const float2 *leafbuf, float2 *arena, float2 *cache, hipStream_t s) {
     if (n_trees <= 0) return;
     hipLaunchKernelGGL(k_small_trees, dim3(n_trees), dim3(256), (size_t)lds_elems * sizeof(float2), s, d_steps,
-                       d_trees, leafbuf, arena);
+                       d_trees, leafbuf, arena, cache);
 }
 
 // ------------------------------------------------------------------ streaming contraction

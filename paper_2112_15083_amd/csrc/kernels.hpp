@@ -35,8 +35,10 @@ struct GemmArgs {
 
 void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_sel, int n_leaves,
                         ProjVals vals, hipStream_t s);
+// d_trees: the first of n_trees subtrees to run; cache: the slice group's
+// global-cache block (subtree roots kept there), or null
 void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int n_trees, int lds_elems,
-                        const float2 *leafbuf, float2 *arena, hipStream_t s);
+                        const float2 *leafbuf, float2 *arena, float2 *cache, hipStream_t s);
 // d_maps: the op's SM_COUNT bit maps in device memory; w: the op's scratch
 // (long form only, else null)
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,

@@ -95,17 +95,35 @@ struct Lowerer {
     std::vector<int> tensor_alloc; // tensor -> alloc index (-1 none)
     std::vector<int> op_first_use;
     int op_counter = 0;
+    // global cache: dep[t] = tensor t depends on the fixed output bits
+    std::vector<char> dep;
+    bool cache = false;
 
-    Lowerer(const Tree &t, const std::vector<Legs> &l, Program &p) : tree(t), legs(l), prog(p) {
+    Lowerer(const Tree &t, const std::vector<Legs> &l, Program &p, const std::vector<char> &leaf_dep, bool cache_)
+        : tree(t), legs(l), prog(p), cache(cache_) {
         nt = t.n_leaves + (int)t.steps.size();
         layout.resize(nt);
         where.resize(nt);
         parent.assign(nt, -1);
         tensor_alloc.assign(nt, -1);
+        dep.assign(nt, 1);
+        for (int i = 0; i < t.n_leaves; i++) dep[i] = leaf_dep[i];
         for (size_t s = 0; s < t.steps.size(); s++) {
             parent[t.steps[s].first] = t.n_leaves + (int)s;
             parent[t.steps[s].second] = t.n_leaves + (int)s;
+            dep[t.n_leaves + s] = dep[t.steps[s].first] | dep[t.steps[s].second];
         }
+        prog.cache = cache;
+    }
+
+    // a tensor the per-batch steps read but do not compute: kept in the cache
+    bool frontier(int t) const { return cache && !dep[t] && (parent[t] < 0 || dep[parent[t]]); }
+    Buf cache_alloc(int64_t size) {
+        Buf b;
+        b.kind = 2;
+        b.off = prog.cache_elems;
+        prog.cache_elems += (size + kAlign - 1) / kAlign * kAlign;
+        return b;
     }
 
     int64_t size_of(int t) const { return (int64_t)1 << legs[t].size(); }
@@ -266,6 +284,10 @@ struct Lowerer {
     }
 
     Buf materialise(int t) {
+        if (frontier(t)) {
+            where[t] = cache_alloc(size_of(t));
+            return where[t];
+        }
         int al = new_alloc(size_of(t), t);
         Buf b;
         b.kind = 0;
@@ -473,7 +495,8 @@ struct Lowerer {
         double by_ = 8.0 * (double)(size_of(a) + size_of(b) + size_of(t));
         prog.streams.push_back(op);
         (void)set_of;
-        prog.ops.push_back({OP_STREAM, (int)prog.streams.size() - 1, f, by_});
+        prog.ops.push_back({OP_STREAM, (int)prog.streams.size() - 1, f, by_, dep[t]});
+        if (!dep[t]) prog.flops_indep += f;
         prog.flops += f;
         prog.bytes += by_;
         op_counter++;
@@ -487,12 +510,18 @@ struct Lowerer {
         op.r = (int)target.size();
         op.perm.resize(op.r);
         for (int i = 0; i < op.r; i++) op.perm[i] = pos_in(target, layout[t][i]);
-        int al = new_alloc(size_of(t), -1);
-        op.dst.kind = 0;
-        op.dst.off = al;
+        // the permuted copy of a cached tensor is what the per-batch steps read
+        int al = -1;
+        if (frontier(t)) {
+            op.dst = cache_alloc(size_of(t));
+        } else {
+            al = new_alloc(size_of(t), -1);
+            op.dst.kind = 0;
+            op.dst.off = al;
+        }
         double by_ = 16.0 * (double)size_of(t);
         prog.permutes.push_back(op);
-        prog.ops.push_back({OP_PERMUTE, (int)prog.permutes.size() - 1, 0.0, by_});
+        prog.ops.push_back({OP_PERMUTE, (int)prog.permutes.size() - 1, 0.0, by_, dep[t]});
         prog.bytes += by_;
         op_counter++;
         perm_alloc_last = al;
@@ -603,7 +632,8 @@ struct Lowerer {
         double f = 8.0 * (double)g.batch * (double)g.M * (double)g.N * (double)g.K;
         double by_ = 8.0 * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
         prog.gemms.push_back(g);
-        prog.ops.push_back({OP_GEMM, (int)prog.gemms.size() - 1, f, by_});
+        prog.ops.push_back({OP_GEMM, (int)prog.gemms.size() - 1, f, by_, dep[t]});
+        if (!dep[t]) prog.flops_indep += f;
         prog.flops += f;
         prog.gemm_flops += f;
         prog.bytes += by_;
@@ -635,13 +665,17 @@ struct Lowerer {
         mark_sub_small();
         // fused small subtrees: roots are small steps whose parent is not small
         in_small.assign(nt, 0);
-        for (int t = tree.n_leaves; t < nt; t++) {
-            if (!sub_small[t]) continue;
-            bool root = parent[t] < 0 || !sub_small[parent[t]];
-            if (!root) continue;
+        // fused small subtrees, those that do not depend on the fixed bits first
+        std::vector<int> small_roots;
+        for (int pass = 0; pass < 2; pass++)
+            for (int t = tree.n_leaves; t < nt; t++)
+                if (sub_small[t] && (parent[t] < 0 || !sub_small[parent[t]]) && dep[t] == pass) small_roots.push_back(t);
+        for (int t : small_roots) {
             Lds lds;
             int first = (int)prog.small_steps.size();
+            const double f0 = prog.flops;
             eval_small(t, lds, true);
+            if (!dep[t]) prog.flops_indep += prog.flops - f0;
             SmallTree st;
             st.first_step = first;
             st.n_steps = (int)prog.small_steps.size() - first;
@@ -649,6 +683,8 @@ struct Lowerer {
             prog.small_lds_elems = std::max(prog.small_lds_elems, lds.peak);
             Buf out = materialise(t);
             prog.small_steps.back().c_off = out.off; // alloc index, resolved below
+            if (out.kind == 2) prog.small_steps.back().c_kind = 3;
+            if (!dep[t]) prog.n_small_indep++;
             // mark inner steps
             std::function<void(int)> mark = [&](int u) {
                 if (u < tree.n_leaves) return;
@@ -707,7 +743,7 @@ struct Lowerer {
             if (b.kind == 0) b.off = allocs[b.off].off;
         };
         for (auto &s : prog.small_steps)
-            if (s.c_kind == 2) s.c_off = allocs[s.c_off].off;
+            if (s.c_kind == 2) s.c_off = allocs[s.c_off].off; // cache offsets (kind 3) are final
         for (auto &s : prog.streams) {
             fix(s.a), fix(s.b), fix(s.c);
             if (s.lk) fix(s.w);
@@ -724,9 +760,9 @@ struct Lowerer {
 // Lower the tree.  leaf_offsets: element offset of each projected leaf in the
 // leaf buffer.  Returns the root layout through `root_layout`.
 Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
-                   std::vector<int> &root_layout) {
+                   const std::vector<char> &leaf_dep, bool cache, std::vector<int> &root_layout) {
     Program prog;
-    Lowerer L(tree, legs, prog);
+    Lowerer L(tree, legs, prog, leaf_dep, cache);
     L.run(leaf_offsets);
     root_layout = L.layout[tree.root()];
     return prog;

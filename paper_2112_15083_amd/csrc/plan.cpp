@@ -9,7 +9,7 @@
 namespace rqc {
 
 Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
-                   std::vector<int> &root_layout);
+                   const std::vector<char> &leaf_dep, bool cache, std::vector<int> &root_layout);
 
 void sort_leaf(Leaf &L) {
     std::vector<int> order(L.legs.size());
@@ -370,7 +370,14 @@ void plan_finish(PlanCore &p) {
     p.kappa = std::exp2(log2_kappa);
     if (!(p.kappa > 0) || !std::isfinite(p.kappa)) fail(RQC_EPLAN, "leaf scale product out of range");
     std::vector<int> root_layout;
-    p.prog = lower_tree(p.tree, legs, leaf_off, root_layout);
+    // leaves that carry a fixed output bit; everything below them depends on
+    // the batch, the rest only on the slice group
+    std::vector<char> is_fixed(sp.n_vars, 0), leaf_dep(nleaves, 0);
+    for (int v : sp.fixed_vars) is_fixed[v] = 1;
+    for (int i = 0; i < nleaves; i++)
+        for (int v : sp.leaves[i].legs)
+            if (is_fixed[v]) leaf_dep[i] = 1;
+    p.prog = lower_tree(p.tree, legs, leaf_off, leaf_dep, p.opts.global_cache != 0, root_layout);
     Program &pg = p.prog;
     pg.leafbuf_elems = buf_off;
     if ((size_t)pg.small_lds_elems * 8 > 65536) fail(RQC_EPLAN, "fused subtree needs more than 64 KiB of LDS");
@@ -406,6 +413,15 @@ void plan_finish(PlanCore &p) {
     I.max_log2_tensor = pg.max_log2;
     I.n_steps = (int32_t)p.tree.steps.size();
     I.n_launches = (int32_t)pg.ops.size() + 2;
+    if (pg.cache) {
+        // one cache block per slice group of the default list, plus one for
+        // calls with their own slice list (recomputed there on every call)
+        const double bytes = 8.0 * (double)pg.cache_elems * (double)(I.n_groups + 1);
+        if (bytes > 128.0 * (1ull << 30))
+            fail(RQC_EPLAN, "global cache would need " + std::to_string(bytes / (1ull << 30)) + " GiB");
+        I.cache_bytes = (int64_t)bytes;
+        I.flops_cached = pg.flops_indep * (double)I.n_groups;
+    }
 }
 
 } // namespace rqc

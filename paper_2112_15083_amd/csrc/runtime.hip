@@ -65,6 +65,8 @@ struct rqc_plan : PlanCore {
     BitMap *d_smaps = nullptr;   // SM_COUNT maps per streaming op
     BitMap *d_rmaps = nullptr;   // root maps: open index, batched slice index
     PermDesc *d_perm = nullptr;  // permute descriptors
+    float2 *d_cache = nullptr;   // global cache: one block per default slice group, plus one spare
+    bool cache_filled = false;
     // profiling
     rqc_profile_t prof{};
     std::vector<PendingEvent> pending;
@@ -148,6 +150,8 @@ struct rqc_plan : PlanCore {
             d_perm = (PermDesc *)dalloc(std::max<size_t>(1, perm_desc.size()) * sizeof(PermDesc));
             if (!perm_desc.empty())
                 HIP_OK(hipMemcpy(d_perm, perm_desc.data(), perm_desc.size() * sizeof(PermDesc), hipMemcpyHostToDevice));
+            if (pg.cache && pg.cache_elems > 0)
+                d_cache = (float2 *)dalloc((size_t)info.cache_bytes);
             HIP_OK(hipMemcpy(d_full, f.data(), f.size() * sizeof(float2), hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(d_sel, sel.data(), sel.size() * sizeof(LeafSel), hipMemcpyHostToDevice));
             if (!pg.small_steps.empty())
@@ -210,7 +214,11 @@ void dump_plan(const rqc_plan &p) {
     std::fprintf(stderr, "plan: %zu fused subtrees (%zu steps, %d LDS elems), %zu ops, arena %lld elems, %lld groups\n",
                  pg.small_trees.size(), pg.small_steps.size(), pg.small_lds_elems, pg.ops.size(),
                  (long long)pg.arena_elems, (long long)p.info.n_groups);
+    if (pg.cache)
+        std::fprintf(stderr, "  global cache: %lld elements per slice group, %d of %zu fused subtrees independent\n",
+                     (long long)pg.cache_elems, pg.n_small_indep, pg.small_trees.size());
     for (const Op &op : pg.ops) {
+        if (pg.cache && op.kind != OP_SMALL) std::fprintf(stderr, "%s", op.dep ? "  [per batch]" : "  [cached]");
         if (op.kind == OP_STREAM) {
             const StreamOp &so = pg.streams[op.index];
             // batch legs: r bits that also index B (all of them, and those in a tile)
@@ -252,79 +260,111 @@ GroupList default_groups(const rqc_plan *p) {
     return g;
 }
 
-void execute(rqc_plan *p, const GroupList &groups, const uint64_t *fixed_bits, int64_t n_batches, void *out_amps,
-             void *out_f64, hipStream_t s) {
+// Which launches of the program a slice group runs: all of them, only those
+// that do not depend on the fixed output bits (filling the global cache), or
+// only those that do (reading the filled cache).
+enum { RUN_ALL = 0, RUN_INDEP = 1, RUN_DEP = 2 };
+
+// One slice group: leaf selection, then the program's launches for `phase`;
+// `slot` picks the group's global-cache block.  Returns the root's address.
+float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hipStream_t s) {
+    const Program &pg = p->prog;
+    float2 *cache = p->d_cache ? p->d_cache + slot * pg.cache_elems : nullptr;
+    auto ptr = [&](const Buf &b) -> float2 * {
+        return (b.kind == 0 ? p->d_arena : (b.kind == 1 ? p->d_leafbuf : cache)) + b.off;
+    };
+    {
+        Timer t(p, s, RQC_K_LEAF, 0, 16.0 * (double)pg.leafbuf_elems);
+        launch_leaf_select(p->d_full, p->d_leafbuf, p->d_sel, (int)p->sel.size(), vals, s);
+    }
+    for (const Op &op : pg.ops) {
+        if (op.kind != OP_SMALL && ((phase == RUN_INDEP && op.dep) || (phase == RUN_DEP && !op.dep))) continue;
+        switch (op.kind) {
+        case OP_SMALL: {
+            const int n = (int)pg.small_trees.size(), ni = pg.n_small_indep;
+            const int first = phase == RUN_DEP ? ni : 0, count = phase == RUN_INDEP ? ni : n - first;
+            Timer t(p, s, RQC_K_SMALL, op.flops, op.bytes);
+            launch_small_trees(p->d_steps, p->d_trees + first, count, pg.small_lds_elems, p->d_leafbuf, p->d_arena,
+                               cache, s);
+            break;
+        }
+        case OP_STREAM: {
+            const StreamOp &so = pg.streams[op.index];
+            Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
+            launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c),
+                          so.lk ? ptr(so.w) : nullptr, s);
+            break;
+        }
+        case OP_PERMUTE: {
+            const PermuteOp &po = pg.permutes[op.index];
+            Timer t(p, s, RQC_K_PERMUTE, op.flops, op.bytes);
+            launch_permute(p->d_perm + op.index, p->perm_desc[op.index].n_tiles, ptr(po.src), ptr(po.dst), s);
+            break;
+        }
+        case OP_GEMM: {
+            const GemmOp &go = pg.gemms[op.index];
+            GemmArgs ga;
+            ga.A = ptr(go.a);
+            ga.B = ptr(go.b);
+            ga.C = ptr(go.c);
+            ga.batch = go.batch;
+            ga.M = go.M;
+            ga.N = go.N;
+            ga.K = go.K;
+            ga.sa = go.sa;
+            ga.sb = go.sb;
+            ga.sc = go.sc;
+            ga.a_kfast = go.a_kfast;
+            ga.b_nfast = go.b_nfast;
+            Timer t(p, s, RQC_K_GEMM, op.flops, op.bytes);
+            launch_gemm(ga, p->opts.precision, p->d_amax, s);
+            break;
+        }
+        }
+    }
+    return ptr(pg.root);
+}
+
+// Run the plan's program for every (batch, slice group) pair.  `is_default`:
+// the groups are the plan's default list (the global cache, if any, holds
+// their fixed-bit-independent parts; it is filled on the first such call).
+void execute(rqc_plan *p, const GroupList &groups, bool is_default, const uint64_t *fixed_bits, int64_t n_batches,
+             void *out_amps, void *out_f64, hipStream_t s) {
     const Program &pg = p->prog;
     const int n_open = (int)p->spec.open_vars.size();
     const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
     const int64_t nout = (int64_t)1 << n_open;
     const double scale = p->kappa / std::sqrt(p->F);
     const int nfix = (int)p->spec.fixed_vars.size();
-    auto ptr = [&](const Buf &b) -> float2 * { return (b.kind == 0 ? p->d_arena : p->d_leafbuf) + b.off; };
+    const bool cached = pg.cache && is_default;
+    auto projection = [&](uint64_t fixed, uint64_t g) {
+        ProjVals vals{};
+        for (int i = 0; i < nfix; i++)
+            if ((fixed >> p->spec.fixed_bit[i]) & 1) vals.w[i >> 6] |= 1ull << (i & 63);
+        for (int u = 0; u < nl; u++)
+            if ((g >> u) & 1) {
+                const int idx = nfix + u;
+                vals.w[idx >> 6] |= 1ull << (idx & 63);
+            }
+        return vals;
+    };
+    if (cached && !p->cache_filled) {
+        for (uint64_t gi = 0; gi < groups.size(); gi++) run_group(p, RUN_INDEP, projection(0, groups[gi]), (int64_t)gi, s);
+        p->cache_filled = true;
+    }
+    // calls with their own slice list use the spare cache block
+    const int64_t spare = p->info.n_groups;
     for (int64_t bi = 0; bi < n_batches; bi++) {
         {
             Timer t(p, s, RQC_K_ACCUM, 0, 16.0 * nout);
             launch_zero(p->d_acc, nout, s);
         }
         for (uint64_t gi = 0; gi < groups.size(); gi++) {
-            const uint64_t g = groups[gi];
-            ProjVals vals{};
-            for (int i = 0; i < nfix; i++)
-                if ((fixed_bits[bi] >> p->spec.fixed_bit[i]) & 1) vals.w[i >> 6] |= 1ull << (i & 63);
-            for (int u = 0; u < nl; u++)
-                if ((g >> u) & 1) {
-                    const int idx = nfix + u;
-                    vals.w[idx >> 6] |= 1ull << (idx & 63);
-                }
-            {
-                Timer t(p, s, RQC_K_LEAF, 0, 16.0 * (double)pg.leafbuf_elems);
-                launch_leaf_select(p->d_full, p->d_leafbuf, p->d_sel, (int)p->sel.size(), vals, s);
-            }
-            for (const Op &op : pg.ops) {
-                switch (op.kind) {
-                case OP_SMALL: {
-                    Timer t(p, s, RQC_K_SMALL, op.flops, op.bytes);
-                    launch_small_trees(p->d_steps, p->d_trees, (int)pg.small_trees.size(), pg.small_lds_elems,
-                                       p->d_leafbuf, p->d_arena, s);
-                    break;
-                }
-                case OP_STREAM: {
-                    const StreamOp &so = pg.streams[op.index];
-                    Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
-                    launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c),
-                                  so.lk ? ptr(so.w) : nullptr, s);
-                    break;
-                }
-                case OP_PERMUTE: {
-                    const PermuteOp &po = pg.permutes[op.index];
-                    Timer t(p, s, RQC_K_PERMUTE, op.flops, op.bytes);
-                    launch_permute(p->d_perm + op.index, p->perm_desc[op.index].n_tiles, ptr(po.src), ptr(po.dst), s);
-                    break;
-                }
-                case OP_GEMM: {
-                    const GemmOp &go = pg.gemms[op.index];
-                    GemmArgs ga;
-                    ga.A = ptr(go.a);
-                    ga.B = ptr(go.b);
-                    ga.C = ptr(go.c);
-                    ga.batch = go.batch;
-                    ga.M = go.M;
-                    ga.N = go.N;
-                    ga.K = go.K;
-                    ga.sa = go.sa;
-                    ga.sb = go.sb;
-                    ga.sc = go.sc;
-                    ga.a_kfast = go.a_kfast;
-                    ga.b_nfast = go.b_nfast;
-                    Timer t(p, s, RQC_K_GEMM, op.flops, op.bytes);
-                    launch_gemm(ga, p->opts.precision, p->d_amax, s);
-                    break;
-                }
-                }
-            }
+            const ProjVals vals = projection(fixed_bits[bi], groups[gi]);
+            float2 *root = cached ? run_group(p, RUN_DEP, vals, (int64_t)gi, s) : run_group(p, RUN_ALL, vals, spare, s);
             {
                 Timer t(p, s, RQC_K_ACCUM, 0, 8.0 * (double)(nout << nb) + 32.0 * nout);
-                launch_accumulate(ptr(pg.root), p->d_rmaps, n_open, nb, p->d_acc, s);
+                launch_accumulate(root, p->d_rmaps, n_open, nb, p->d_acc, s);
             }
         }
         {
@@ -368,7 +408,7 @@ std::vector<double> gpu_norms(const rqc_plan_opts &outer, const NetSpec &spec, c
     std::vector<double2> host(n);
     try {
         uint64_t zero = 0;
-        execute(&q, default_groups(&q), &zero, 1, amps, r64, nullptr);
+        execute(&q, default_groups(&q), true, &zero, 1, amps, r64, nullptr);
         HIP_OK(hipMemcpy(host.data(), r64, n * sizeof(double2), hipMemcpyDeviceToHost));
     } catch (...) {
         (void)hipFree(amps);
@@ -533,7 +573,7 @@ rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64
         if (dev != p->device) fail(RQC_EDEVICE, "plan belongs to another device");
         const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
         if (!slice_ids) {
-            execute(p, default_groups(p), fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
+            execute(p, default_groups(p), true, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
             return;
         }
         if (n_slices < 0) fail(RQC_EINVAL, "negative slice count");
@@ -562,7 +602,7 @@ rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64
         }
         GroupList gl;
         gl.list = &groups;
-        execute(p, gl, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
+        execute(p, gl, false, fixed_bits, n_batches, out_amps, out_f64, (hipStream_t)hip_stream);
     });
 }
 

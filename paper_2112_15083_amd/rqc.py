@@ -36,7 +36,8 @@ class PlanOpts(ctypes.Structure):
                 ("partial_count", ctypes.c_int32), ("partial_total_slices", ctypes.c_int64),
                 ("path_trials", ctypes.c_int32),
                 ("path_seed", ctypes.c_uint64), ("profile", ctypes.c_int32), ("dry_run", ctypes.c_int32),
-                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+                ("global_cache", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -47,7 +48,8 @@ class PlanInfo(ctypes.Structure):
                 ("gemm_flop_share", ctypes.c_double), ("bytes_per_batch", ctypes.c_double),
                 ("max_log2_tensor", ctypes.c_int32), ("n_steps", ctypes.c_int32),
                 ("n_launches", ctypes.c_int32), ("n_groups", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double)]
+                ("workspace_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
+                ("cache_bytes", ctypes.c_int64), ("flops_cached", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -69,6 +69,26 @@ def test_dry_run_plans(rqc):
         assert all(v >= cfg["rows"] * cfg["cols"] for v in legs)
 
 
+def test_global_cache_plan_report(rqc):
+    """The global cache covers exactly the work that does not depend on the
+    fixed bits: everything when all qubits are open, part of it otherwise, and
+    it holds one block per slice group plus a spare."""
+    cfg = synthetic.CONFIGS["tiny"]
+    t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"])
+    info = rqc.plan_info(rqc.plan_create(rqc.load_circuit(t), cfg["open_qubits"], dry_run=1, global_cache=1))
+    assert info["flops_cached"] == info["flops_per_batch"]
+    assert info["cache_bytes"] == 2 * 8 * 2 ** 12  # the final 2^12 tensor, one group + spare
+    t = synthetic.circuit_text(4, 4, 10, 1)
+    c = rqc.load_circuit(t)
+    plain = rqc.plan_info(rqc.plan_create(c, list(range(10, 16)), dry_run=1, n_sliced_target=3,
+                                          max_log2_batched=1, path_seed=1))
+    info = rqc.plan_info(rqc.plan_create(c, list(range(10, 16)), dry_run=1, n_sliced_target=3,
+                                         max_log2_batched=1, path_seed=1, global_cache=1))
+    assert plain["cache_bytes"] == 0 and plain["flops_cached"] == 0
+    assert 0 < info["flops_cached"] < info["flops_per_batch"] == plain["flops_per_batch"]
+    assert info["cache_bytes"] % (8 * (info["n_groups"] + 1)) == 0
+
+
 def test_memory_target_slicing(rqc):
     cfg = synthetic.CONFIGS["mid"]
     t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"])

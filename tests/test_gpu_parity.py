@@ -177,3 +177,63 @@ def test_sampler_short_status(rqc):
     out = torch.zeros(1000, dtype=torch.int64, device="cuda")
     n_out, st, code = rqc.rejection_sample(dev, [0], cfg["open_qubits"], 12, 1000, out, pick_steps=100)
     assert code == rqc.ESHORT and n_out < 1000
+
+
+@pytest.mark.parametrize("rows,cols,cycles,n_open,n_sliced,batched,seed", [
+    (4, 4, 10, 6, 3, 1, 1),      # looped slices: one cache block per group
+    (4, 5, 12, 8, 4, 2, 12),     # mixed looped / batched, GEMM steps
+    (3, 4, 8, 12, 0, 28, 13),    # all qubits open: the whole contraction is cached
+])
+def test_global_cache_bitwise_equal(rqc, rows, cols, cycles, n_open, n_sliced, batched, seed):
+    """The global cache (parts independent of the fixed bits computed once per
+    slice group) changes no bit of any result, over successive calls with
+    different fixed bits, and stays within the bar of the oracle."""
+    import torch
+    text = circuit(rows, cols, cycles, seed=seed)
+    n = rows * cols
+    open_q = list(range(n - n_open, n))
+    c = rqc.load_circuit(text)
+    opts = dict(n_sliced_target=n_sliced, max_log2_batched=batched, path_seed=seed)
+    # (the plan choice is deterministic, so both plans share one tree)
+    plain = rqc.plan_create(c, open_q, **opts)
+    cached = rqc.plan_create(c, open_q, global_cache=1, **opts)
+    info = rqc.plan_info(cached)
+    assert info["cache_bytes"] > 0 and 0 < info["flops_cached"] <= info["flops_per_batch"]
+    for call in range(3):
+        fixed = synthetic.fixed_bits_batch(n, open_q, 3000 + 10 * seed + call, 2)
+        o1 = torch.empty((2, 1 << n_open, 2), dtype=torch.float32, device="cuda")
+        o2 = torch.empty_like(o1)
+        rqc.contract_amplitudes(plain, fixed, o1)
+        rqc.contract_amplitudes(cached, fixed, o2)
+        torch.cuda.synchronize()
+        assert torch.equal(o1, o2), call
+        a = o2.cpu().numpy()
+        ref = oracle_batches(text, fixed, open_q)
+        for b in range(2):
+            assert rel_l2(a[b, :, 0] + 1j * a[b, :, 1], ref[b]) <= TOL
+    # an explicit slice list bypasses the cache and still agrees bit for bit
+    ids = list(range(info["n_slices"]))
+    o1 = torch.empty((1, 1 << n_open, 2), dtype=torch.float32, device="cuda")
+    o2 = torch.empty_like(o1)
+    rqc.contract_amplitudes(plain, [5], o1, slice_ids=ids)
+    rqc.contract_amplitudes(cached, [5], o2, slice_ids=ids)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+
+
+def test_global_cache_split_precision(rqc):
+    """Cached and uncached plans agree bitwise in the bf16x3 mode too."""
+    import torch
+    text = circuit(4, 5, 12, seed=14)
+    open_q = list(range(10, 20))
+    c = rqc.load_circuit(text)
+    opts = dict(n_sliced_target=3, precision=rqc.BF16X3, path_seed=2)
+    plain = rqc.plan_create(c, open_q, **opts)
+    cached = rqc.plan_create(c, open_q, global_cache=1, **opts)
+    fixed = synthetic.fixed_bits_batch(20, open_q, 4000, 3)
+    o1 = torch.empty((3, 1 << 10, 2), dtype=torch.float32, device="cuda")
+    o2 = torch.empty_like(o1)
+    rqc.contract_amplitudes(plain, fixed, o1)
+    rqc.contract_amplitudes(cached, fixed, o2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
