@@ -204,16 +204,19 @@ def run_mid_like(args, rqc, torch):
         # depend on the fixed bits are computed once per slice group (the fill)
         # and every batch then contracts only the rest.  Reported beside the
         # headline value, which recomputes everything on every step.
-        ref_out = out.clone()
         cplan = rqc.plan_create(circ, open_q, n_sliced_target=n_sliced, path_trials=args.path_trials,
                                 precision=prec, global_cache=1)
         cinfo = rqc.plan_info(cplan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        step(args.warmup + args.steps, pl=cplan)
+        step(0, pl=cplan)  # fills the cache; call 0 has stored oracle amplitudes
         torch.cuda.synchronize()
         fill_s = time.perf_counter() - t0
-        same = bool(torch.equal(out, ref_out))
+        c_rel = None
+        if os.path.exists(gold):
+            a = out.cpu().numpy()[0]
+            ref = np.load(gold)
+            c_rel = float(np.linalg.norm(a[:, 0].astype(np.float64) + 1j * a[:, 1] - ref) / np.linalg.norm(ref))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -225,9 +228,10 @@ def run_mid_like(args, rqc, torch):
             "fill_and_first_step_ms": 1e3 * fill_s, "cache_gib": cinfo["cache_bytes"] / 2 ** 30,
             "flops_cached_share": cinfo["flops_cached"] / cinfo["flops_per_batch"],
             "tflops_per_step_executed": args.steps * (cinfo["flops_per_batch"] - cinfo["flops_cached"]) / c_el / 1e12,
-            "bitwise_equal_to_uncached": same,
-            "note": "same steps with the fixed-bit-independent parts computed once per slice group (filled "
-                    "on the first call, not in this timing); amortised over many batches of one circuit"}
+            "rel_l2_vs_fp64": c_rel,
+            "note": "same steps on a plan whose fixed-bit-independent parts are computed once per slice group "
+                    "(filled on the first call, not in this timing; the planner picks the tree by per-batch "
+                    "cost), amortised over many batches of one circuit"}
         del cplan
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, text)

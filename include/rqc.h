@@ -213,6 +213,11 @@ rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_
 rqc_status rqc_plan_info(const rqc_plan *p, rqc_plan_info_t *info);
 /* Sliced variable ids in slice-id bit order (bit t of a slice id = legs[t]). */
 rqc_status rqc_plan_sliced_legs(const rqc_plan *p, int32_t *legs, int32_t cap, int32_t *count);
+/* The plan's contraction tree as SSA pairs, in the form rqc_plan_create takes
+   (pairs[2s], pairs[2s+1] for step s; cap and *count are pair counts), so that
+   another plan can be built on the same tree (the path the Sec. I tree T is
+   contracted along). */
+rqc_status rqc_plan_path(const rqc_plan *p, int32_t *pairs, int32_t cap, int32_t *count);
 /* Partial slicing results: S (variable ids, bit t of an index i = S[t]), the
    kept indices X in selection order, and R[0 .. 2^k) (host arrays; any may be
    NULL; caps are element counts). */

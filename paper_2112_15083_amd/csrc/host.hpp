@@ -186,6 +186,8 @@ struct GemmOp {     // C[b][m][n] = sum_k A[b][m][k] B[b][k][n] (complex)
     int b_nfast;    // B element (k,n) at k*N + n if 1, n*K + k if 0
     int c_nfast;    // C element (m,n) at m*N + n if 1, n*M + m if 0
     int64_t sa, sb, sc; // batch strides (elements)
+    int ksplit = 1; // > 1: K in ksplit ranges, partial sums in w ([range][batch][m][n]), added in order
+    Buf w;
 };
 
 struct Op {

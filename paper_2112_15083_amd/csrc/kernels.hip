@@ -741,8 +741,11 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
     // workgroups go round-robin over the 8 XCDs; give each XCD a contiguous
     // run of tiles, so that tiles sharing an operand panel share that XCD's L2
     const int64_t nblk = gridDim.x;
-    const int64_t bid = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
-                                         : (int64_t)blockIdx.x;
+    const int64_t bid0 = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
+                                          : (int64_t)blockIdx.x;
+    // with split K the grid is ksplit copies of the tile grid, one per K range
+    const int64_t ntiles = ntn * ntm * g.batch;
+    const int64_t bid = bid0 % ntiles, krange = bid0 / ntiles;
     const int64_t bz = bid / (ntn * ntm);
     // consecutive tiles share the larger operand's panel: m runs fastest when
     // B is the larger operand (N > M), n otherwise
@@ -750,7 +753,7 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
     const int64_t n0 = (g.m_fast ? (bid / ntm) % ntn : bid % ntn) * BN;
     const float2 *A = g.A + bz * g.sa;
     const float2 *B = g.B + bz * g.sb;
-    float2 *C = g.C + bz * g.sc;
+    float2 *C = g.ksplit > 1 ? g.W + (krange * g.batch + bz) * g.M * g.N : g.C + bz * g.sc;
     const int64_t M = g.M, N = g.N, K = g.K;
 
     // per-thread global coordinates of its operand chunk
@@ -800,13 +803,14 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
 #pragma unroll
             for (int v = 0; v < 16; v++) cre[i][j][v] = 0.f, cim[i][j][v] = 0.f;
 
-    const int nk = (int)(K / BK);
-    gload(0);
+    const int64_t kb = krange * (K / g.ksplit); // this workgroup's K range
+    const int nk = (int)(K / g.ksplit / BK);
+    gload(kb);
     sstore(0);
     __syncthreads();
     for (int kt = 0; kt < nk; kt++) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+        if (kt + 1 < nk) gload(kb + (int64_t)(kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 2) {
             const int kr = kk + (lane >> 5);
@@ -914,8 +918,11 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
     // workgroups go round-robin over the 8 XCDs; give each XCD a contiguous
     // run of tiles, so that tiles sharing an operand panel share that XCD's L2
     const int64_t nblk = gridDim.x;
-    const int64_t bid = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
-                                         : (int64_t)blockIdx.x;
+    const int64_t bid0 = (nblk & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3)
+                                          : (int64_t)blockIdx.x;
+    // with split K the grid is ksplit copies of the tile grid, one per K range
+    const int64_t ntiles = ntn * ntm * g.batch;
+    const int64_t bid = bid0 % ntiles, krange = bid0 / ntiles;
     const int64_t bz = bid / (ntn * ntm);
     // consecutive tiles share the larger operand's panel: m runs fastest when
     // B is the larger operand (N > M), n otherwise
@@ -923,7 +930,7 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
     const int64_t n0 = (g.m_fast ? (bid / ntm) % ntn : bid % ntn) * BN;
     const float2 *A = g.A + bz * g.sa;
     const float2 *B = g.B + bz * g.sb;
-    float2 *C = g.C + bz * g.sc;
+    float2 *C = g.ksplit > 1 ? g.W + (krange * g.batch + bz) * g.M * g.N : g.C + bz * g.sc;
     const int64_t M = g.M, N = g.N, K = g.K;
     int ea = 0, eb = 0;
     if (F16) {
@@ -1031,15 +1038,16 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
     // stage s lives in register slot s & 1 and LDS buffer s & 1; loads past
     // the last stage re-read it (unused), so that every iteration issues the
     // same loads and the waits before staging cover exactly one stage
-    const int nk = (int)(K / BK);
-    gload(0, 0);
-    gload(1, (int64_t)std::min(1, nk - 1) * BK);
+    const int64_t kb = krange * (K / g.ksplit); // this workgroup's K range
+    const int nk = (int)(K / g.ksplit / BK);
+    gload(0, kb);
+    gload(1, kb + (int64_t)std::min(1, nk - 1) * BK);
     sstore(0, 0);
     __syncthreads();
     // two stages per trip, so that register slots are compile-time indices
     auto stage = [&](auto par, int kt) {
         constexpr int cur = decltype(par)::value;
-        gload(cur, (int64_t)std::min(kt + 2, nk - 1) * BK); // stage kt is already in LDS
+        gload(cur, kb + (int64_t)std::min(kt + 2, nk - 1) * BK); // stage kt is already in LDS
         compute(cur);
         if (kt + 1 < nk) sstore(cur ^ 1, cur ^ 1);
         __syncthreads();
@@ -1079,7 +1087,7 @@ __global__ void k_zero_u32(unsigned *p, int n) {
 
 template <int BM, int BN, bool F16>
 static void split_dispatch(const GemmArgs &g, const unsigned *amax, hipStream_t s) {
-    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch));
+    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch * g.ksplit));
     if (g.a_kfast && g.b_nfast) hipLaunchKernelGGL((k_cgemm_split<BM, BN, 1, 1, F16>), grid, dim3(256), 0, s, g, amax);
     else if (g.a_kfast) hipLaunchKernelGGL((k_cgemm_split<BM, BN, 1, 0, F16>), grid, dim3(256), 0, s, g, amax);
     else if (g.b_nfast) hipLaunchKernelGGL((k_cgemm_split<BM, BN, 0, 1, F16>), grid, dim3(256), 0, s, g, amax);
@@ -1103,16 +1111,43 @@ static void split_gemm(const GemmArgs &g, unsigned *amax, hipStream_t s) {
 
 template <int BM, int BN>
 static void gemm_dispatch(const GemmArgs &g, hipStream_t s) {
-    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch));
+    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch * g.ksplit));
     if (g.a_kfast && g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 1>), grid, dim3(256), 0, s, g);
     else if (g.a_kfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 0>), grid, dim3(256), 0, s, g);
     else if (g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 1>), grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 0>), grid, dim3(256), 0, s, g);
 }
 
+void launch_gemm_tiles(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s);
+
+// Split K: C = sum over ranges r (ascending) of W[r], one output per thread.
+__global__ void __launch_bounds__(256) k_gemm_ksum(const float2 *__restrict__ W, float2 *__restrict__ C,
+                                                   int64_t n, int64_t mn, int64_t sc, int ksplit) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float2 acc = W[i];
+        for (int r = 1; r < ksplit; r++) {
+            const float2 x = W[(int64_t)r * n + i];
+            acc.x += x.x;
+            acc.y += x.y;
+        }
+        C[(i / mn) * sc + i % mn] = acc;
+    }
+}
+
 void launch_gemm(const GemmArgs &g_in, int precision, unsigned *amax, hipStream_t s) {
     GemmArgs g = g_in;
     g.m_fast = g.N > g.M;
+    if (g.ksplit < 1 || (g.ksplit > 1 && (!g.W || g.K % (8LL * g.ksplit) != 0)))
+        fail(RQC_EPLAN, "GEMM K split does not fit its kernel");
+    launch_gemm_tiles(g, precision, amax, s);
+    if (g.ksplit > 1) {
+        const int64_t n = g.batch * g.M * g.N;
+        hipLaunchKernelGGL(k_gemm_ksum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 256 * 16)), dim3(256), 0, s,
+                           g.W, g.C, n, g.M * g.N, g.sc, g.ksplit);
+    }
+}
+
+void launch_gemm_tiles(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s) {
     // the split kernels stage 16 complex k per step; shorter contractions stay FP32
     if (precision == RQC_BF16X3 && g.K >= 16) return split_gemm<false>(g, amax, s);
     if (precision == RQC_FP16X3 && g.K >= 16) return split_gemm<true>(g, amax, s);

@@ -31,6 +31,8 @@ struct GemmArgs {
     int64_t sa, sb, sc;
     int a_kfast, b_nfast;
     int m_fast = 0; // tile order: m fastest (set by the launcher)
+    int ksplit = 1; // > 1: K in ksplit ranges, partial sums in W ([range][batch][m][n]), then added in order
+    float2 *W = nullptr;
 };
 
 void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_sel, int n_leaves,

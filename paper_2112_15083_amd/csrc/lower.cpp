@@ -622,6 +622,19 @@ struct Lowerer {
         g.sa = g.M * g.K;
         g.sb = g.K * g.N;
         g.sc = g.M * g.N;
+        // when the output tiles (the launcher's 128 or 64 a side) cannot fill
+        // the chip, split K into ranges of at least 128 whose partial sums go
+        // to scratch and are added in range order
+        {
+            const int64_t tiles = g.batch * (g.M / (g.M >= 128 ? 128 : 64)) * (g.N / (g.N >= 128 ? 128 : 64));
+            int ks = 1;
+            while (tiles * ks < 1024 && g.K / (2 * ks) >= 128) ks *= 2;
+            if (ks > 1) {
+                g.ksplit = ks;
+                g.w.kind = 0;
+                g.w.off = new_alloc((int64_t)ks * g.batch * g.M * g.N, -1);
+            }
+        }
         std::vector<int> LC = fbord;
         LC.insert(LC.end(), faord.begin(), faord.end());
         LC.insert(LC.end(), bord.begin(), bord.end());
@@ -749,7 +762,10 @@ struct Lowerer {
             if (s.lk) fix(s.w);
         }
         for (auto &p : prog.permutes) fix(p.src), fix(p.dst);
-        for (auto &g : prog.gemms) fix(g.a), fix(g.b), fix(g.c);
+        for (auto &g : prog.gemms) {
+            fix(g.a), fix(g.b), fix(g.c);
+            if (g.ksplit > 1) fix(g.w);
+        }
         for (int t = 0; t < nt; t++)
             if (where[t].kind == 0 && tensor_alloc[t] >= 0) where[t].off = allocs[tensor_alloc[t]].off;
         prog.root = where[root];

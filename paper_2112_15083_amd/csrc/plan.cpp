@@ -124,11 +124,16 @@ double estimate_seconds(const PlanCore &p) {
     // measured rates on MI355X: complex64 GEMM ~80% of FP32 MFMA, split GEMM
     // ~1/3 of its 3-product ceiling, HBM-bound kernels 4.5-5.5 TB/s
     const double gemm_rate = p.opts.precision == RQC_C64 ? 0.8 * 157.3e12 : 0.33 * 838.9e12;
+    // with the global cache a batch runs only the fixed-bit-dependent launches;
+    // the rest is filled once and weighed as shared by many batches
+    const double w_indep = pg.cache ? 1.0 / 256 : 1.0;
     double t = 20e-6;
     for (const Op &op : pg.ops) {
-        if (op.kind == OP_GEMM) t += std::max(op.flops / gemm_rate, op.bytes / 5.5e12) + 4e-6;
-        else if (op.kind == OP_SMALL) t += 70e-6;
-        else t += op.bytes / 4.5e12 + 4e-6;
+        double dt;
+        if (op.kind == OP_GEMM) dt = std::max(op.flops / gemm_rate, op.bytes / 5.5e12) + 4e-6;
+        else if (op.kind == OP_SMALL) dt = 70e-6;
+        else dt = op.bytes / 4.5e12 + 4e-6;
+        t += (op.kind == OP_SMALL || op.dep) ? dt : w_indep * dt;
     }
     return t * (double)std::max<int64_t>(1, p.info.n_groups);
 }
@@ -173,10 +178,13 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
         std::vector<SearchResult> rs = search_tree(path_legs, nv, kept, sp.forbidden, user_sliced,
                                                    p.opts.max_log2_tensor, p.opts.n_sliced_target, trials,
                                                    p.opts.path_seed);
-        // the few best by the proxy cost are lowered and compared by estimated time
+        // the few best by the proxy cost are lowered and compared by estimated
+        // time (more of them with the global cache, whose per-batch cost the
+        // proxy does not see)
         size_t best = 0;
         double best_t = 1e300;
-        for (size_t i = 0; i < rs.size() && i < 8; i++) {
+        const size_t n_lower = p.opts.global_cache ? 32 : 8;
+        for (size_t i = 0; i < rs.size() && i < n_lower; i++) {
             PlanCore q;
             q.opts = p.opts;
             q.spec = p.spec;

@@ -234,8 +234,8 @@ void dump_plan(const rqc_plan &p) {
                          op.flops, op.bytes);
         } else if (op.kind == OP_GEMM) {
             const GemmOp &g = pg.gemms[op.index];
-            std::fprintf(stderr, "  gemm b=%lld M=%lld N=%lld K=%lld ak=%d bn=%d flops=%.3g\n", (long long)g.batch,
-                         (long long)g.M, (long long)g.N, (long long)g.K, g.a_kfast, g.b_nfast, op.flops);
+            std::fprintf(stderr, "  gemm b=%lld M=%lld N=%lld K=%lld ak=%d bn=%d ks=%d flops=%.3g\n", (long long)g.batch,
+                         (long long)g.M, (long long)g.N, (long long)g.K, g.a_kfast, g.b_nfast, g.ksplit, op.flops);
         } else if (op.kind == OP_PERMUTE) {
             std::fprintf(stderr, "  permute r=%d bytes=%.3g\n", pg.permutes[op.index].r, op.bytes);
         } else {
@@ -316,6 +316,8 @@ float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hi
             ga.sc = go.sc;
             ga.a_kfast = go.a_kfast;
             ga.b_nfast = go.b_nfast;
+            ga.ksplit = go.ksplit;
+            ga.W = go.ksplit > 1 ? ptr(go.w) : nullptr;
             Timer t(p, s, RQC_K_GEMM, op.flops, op.bytes);
             launch_gemm(ga, p->opts.precision, p->d_amax, s);
             break;
@@ -501,6 +503,17 @@ rqc_status rqc_plan_sliced_legs(const rqc_plan *p, int32_t *legs, int32_t cap, i
         if (!p) fail(RQC_EINVAL, "null plan");
         if (count) *count = (int32_t)p->sliced.size();
         for (size_t i = 0; legs && i < p->sliced.size() && (int32_t)i < cap; i++) legs[i] = p->sliced[i];
+    });
+}
+
+rqc_status rqc_plan_path(const rqc_plan *p, int32_t *pairs, int32_t cap, int32_t *count) {
+    return guard([&] {
+        if (!p) fail(RQC_EINVAL, "null plan");
+        if (count) *count = (int32_t)p->tree.steps.size();
+        for (size_t s = 0; pairs && s < p->tree.steps.size() && (int32_t)s < cap; s++) {
+            pairs[2 * s] = p->tree.steps[s].first;
+            pairs[2 * s + 1] = p->tree.steps[s].second;
+        }
     });
 }
 

@@ -81,6 +81,7 @@ _sig = {
                         ctypes.POINTER(PlanOpts), ctypes.POINTER(_P)],
     "rqc_plan_info": [_P, ctypes.POINTER(PlanInfo)],
     "rqc_plan_sliced_legs": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "rqc_plan_path": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "rqc_plan_partial": [_P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int64],
     "rqc_plan_slices": [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
     "rqc_plan_profile": [_P, ctypes.POINTER(Profile)],
@@ -227,6 +228,15 @@ def plan_sliced_legs(p: Plan):
     arr = (ctypes.c_int32 * max(1, n.value))()
     _check(_lib.rqc_plan_sliced_legs(p.handle, arr, n.value, ctypes.byref(n)))
     return list(arr)[: n.value]
+
+
+def plan_path(p: Plan):
+    """The plan's contraction tree as SSA pairs (the `path` plan_create takes)."""
+    n = ctypes.c_int32()
+    _check(_lib.rqc_plan_path(p.handle, None, 0, ctypes.byref(n)))
+    arr = (ctypes.c_int32 * max(2, 2 * n.value))()
+    _check(_lib.rqc_plan_path(p.handle, arr, n.value, ctypes.byref(n)))
+    return [(arr[2 * s], arr[2 * s + 1]) for s in range(n.value)]
 
 
 def plan_partial(p: Plan):

@@ -89,6 +89,24 @@ def test_global_cache_plan_report(rqc):
     assert info["cache_bytes"] % (8 * (info["n_groups"] + 1)) == 0
 
 
+def test_plan_path_round_trip(rqc):
+    """A plan's path and sliced legs rebuild the same plan."""
+    t = synthetic.circuit_text(4, 5, 12, 12)
+    c = rqc.load_circuit(t)
+    p1 = rqc.plan_create(c, list(range(12, 20)), dry_run=1, n_sliced_target=4, path_seed=12)
+    path = rqc.plan_path(p1)
+    n_leaves = len(path) + 1
+    used = set()
+    for s_, (a, b) in enumerate(path):  # SSA pairs: each tensor used once, results numbered in order
+        assert a != b and a < n_leaves + s_ and b < n_leaves + s_ and a not in used and b not in used
+        used.update((a, b))
+    p2 = rqc.plan_create(c, list(range(12, 20)), dry_run=1, path=path, sliced_legs=rqc.plan_sliced_legs(p1))
+    i1, i2 = rqc.plan_info(p1), rqc.plan_info(p2)
+    assert rqc.plan_path(p2) == path
+    for k in ("flops_per_batch", "n_batched", "n_slices", "max_log2_tensor", "n_launches"):
+        assert i1[k] == i2[k], k
+
+
 def test_memory_target_slicing(rqc):
     cfg = synthetic.CONFIGS["mid"]
     t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"])

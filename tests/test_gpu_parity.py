@@ -194,9 +194,11 @@ def test_global_cache_bitwise_equal(rqc, rows, cols, cycles, n_open, n_sliced, b
     open_q = list(range(n - n_open, n))
     c = rqc.load_circuit(text)
     opts = dict(n_sliced_target=n_sliced, max_log2_batched=batched, path_seed=seed)
-    # (the plan choice is deterministic, so both plans share one tree)
-    plain = rqc.plan_create(c, open_q, **opts)
     cached = rqc.plan_create(c, open_q, global_cache=1, **opts)
+    # the uncached plan on the same tree and sliced legs (the planner's choice
+    # differs with the cache, whose per-batch cost it minimises)
+    plain = rqc.plan_create(c, open_q, path=rqc.plan_path(cached), sliced_legs=rqc.plan_sliced_legs(cached),
+                            max_log2_batched=batched)
     info = rqc.plan_info(cached)
     assert info["cache_bytes"] > 0 and 0 < info["flops_cached"] <= info["flops_per_batch"]
     for call in range(3):
@@ -227,9 +229,9 @@ def test_global_cache_split_precision(rqc):
     text = circuit(4, 5, 12, seed=14)
     open_q = list(range(10, 20))
     c = rqc.load_circuit(text)
-    opts = dict(n_sliced_target=3, precision=rqc.BF16X3, path_seed=2)
-    plain = rqc.plan_create(c, open_q, **opts)
-    cached = rqc.plan_create(c, open_q, global_cache=1, **opts)
+    cached = rqc.plan_create(c, open_q, global_cache=1, n_sliced_target=3, precision=rqc.BF16X3, path_seed=2)
+    plain = rqc.plan_create(c, open_q, path=rqc.plan_path(cached), sliced_legs=rqc.plan_sliced_legs(cached),
+                            precision=rqc.BF16X3)
     fixed = synthetic.fixed_bits_batch(20, open_q, 4000, 3)
     o1 = torch.empty((3, 1 << 10, 2), dtype=torch.float32, device="cuda")
     o2 = torch.empty_like(o1)
@@ -237,3 +239,22 @@ def test_global_cache_split_precision(rqc):
     rqc.contract_amplitudes(cached, fixed, o2)
     torch.cuda.synchronize()
     assert torch.equal(o1, o2)
+
+
+@pytest.mark.parametrize("rows,cols,cycles,n_open,n_sliced,seed,precision,tol", [
+    (4, 6, 14, 8, 4, 3, 0, TOL),      # a GEMM with K split in 2 ranges
+    (5, 5, 14, 12, 5, 4, 0, TOL),     # K = 16384 split in 32 ranges
+    (5, 5, 14, 12, 5, 4, 1, 2e-4),    # the same in bf16x3
+])
+def test_split_k_gemm_steps(rqc, rows, cols, cycles, n_open, n_sliced, seed, precision, tol):
+    """Plans whose GEMMs have too few output tiles to fill the chip split K into
+    ranges summed in order; parity with the oracle."""
+    text = circuit(rows, cols, cycles, seed=seed)
+    n = rows * cols
+    open_q = list(range(n - n_open, n))
+    fixed = synthetic.fixed_bits_batch(n, open_q, 5000 + seed, 2)
+    amps, _, info, _ = run_amplitudes(rqc, text, open_q, fixed, n_sliced_target=n_sliced, path_seed=seed,
+                                      precision=precision)
+    ref = oracle_batches(text, fixed, open_q)
+    for b in range(2):
+        assert rel_l2(amps[b], ref[b]) <= tol, (b, rel_l2(amps[b], ref[b]))
