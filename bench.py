@@ -118,7 +118,7 @@ def run_mid_like(args, rqc, torch):
         partial = dict(target_fidelity=args.target_fidelity)
     n_sliced = args.partial_sliced if args.target_fidelity else N_SLICED[args.config]
     plan = rqc.plan_create(circ, open_q, n_sliced_target=n_sliced, path_trials=args.path_trials,
-                           precision=prec, profile=1, **partial)
+                           path_seed=args.path_seed, precision=prec, profile=1, **partial)
     plan_s = time.perf_counter() - t0
     info = rqc.plan_info(plan)
     stream = torch.cuda.current_stream()
@@ -205,7 +205,7 @@ def run_mid_like(args, rqc, torch):
         # and every batch then contracts only the rest.  Reported beside the
         # headline value, which recomputes everything on every step.
         cplan = rqc.plan_create(circ, open_q, n_sliced_target=n_sliced, path_trials=args.path_trials,
-                                precision=prec, global_cache=1)
+                                path_seed=args.path_seed, precision=prec, global_cache=1)
         cinfo = rqc.plan_info(cplan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -348,6 +348,7 @@ def main():
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path-trials", type=int, default=256)
+    ap.add_argument("--path-seed", type=int, default=0)
     ap.add_argument("--large-prefix", type=int, default=16)
     ap.add_argument("--target-fidelity", type=float, default=0.0)
     ap.add_argument("--partial-sliced", type=int, default=12)

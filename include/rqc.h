@@ -148,6 +148,8 @@ typedef struct {
     double flops_cached;       /* of flops_per_batch, the part that does not
                                   depend on the fixed bits (computed once per
                                   plan when global_cache is set) */
+    double est_seconds;        /* the planner's estimate of one batch's GPU time
+                                  (what it minimises over candidate trees) */
 } rqc_plan_info_t;
 
 typedef struct {

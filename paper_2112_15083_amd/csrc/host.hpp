@@ -94,7 +94,7 @@ struct SearchResult {
     std::vector<int> sliced;
     double log2cost = 0;
 };
-// All trials, best proxy cost first.
+// The reconfigured best trials (a sixteenth of `trials`, at least 8), best proxy cost first.
 std::vector<SearchResult> search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
                                       const std::vector<char> &forbidden, const std::vector<int> *user_sliced,
                                       int max_log2_tensor, int n_target, int trials, uint64_t seed);

@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) k_stream_ky(const float2 *__restrict__ A,
 }
 
 // Short contraction on matrix cores.  Per tile of R = 2^L rows (64..256):
-// C[r][f] = sum_y A[r][y] B_r[y][f] with K = 2^KC <= 32 and F = 2^nf <= 32.
+// C[r][f] = sum_y A[r][y] B_r[y][f] with K = 2^KC <= 32 and F = 2^nf <= 64.
 // As a real product, [A_re | A_im] interleaved per y (row length 2K) times the
 // 2K x 2F block matrix with entries B'[2y+c][2f+d] = (B_re, B_im; -B_im, B_re)
 // [c][d] gives C interleaved per f, i.e. the complex rows of C.  Each wave owns
@@ -335,14 +335,19 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
     // tile's size the pair index wraps, so the extra copies read and write
     // identical values: all tile loads and stores are unconditional, which
     // lets the compiler wait for exactly the loads it needs.
+    constexpr int CPT = NC == 8 ? 8 : 4; // C pairs per thread (tiles of 2^12 C elements for 2^nf = 64)
     const int hA = (R << KC) >> 1, hC = (R << nf) >> 1;
-    uint32_t oA[4], sA[4], oC[4], sC[4];
+    uint32_t oA[4], sA[4], oC[CPT], sC[CPT];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        const int ea = 2 * ((tid + 256 * k) & (hA - 1)), ec = 2 * ((tid + 256 * k) & (hC - 1));
+        const int ea = 2 * ((tid + 256 * k) & (hA - 1));
         oA[k] = (uint32_t)map_apply(maps[SM_EA], ea) * 8u;
         sA[k] = (uint32_t)(map_apply(maps[SM_ER], ea) * KP + map_apply(maps[SM_EY], ea)) |
                 (uint32_t)(map_apply(maps[SM_ER], ea + 1) * KP + map_apply(maps[SM_EY], ea + 1)) << 16;
+    }
+#pragma unroll
+    for (int k = 0; k < CPT; k++) {
+        const int ec = 2 * ((tid + 256 * k) & (hC - 1));
         oC[k] = (uint32_t)map_apply(maps[SM_EC], ec) * 8u;
         sC[k] = (uint32_t)(map_apply(maps[SM_ER2], ec) * FP + map_apply(maps[SM_EF], ec)) |
                 (uint32_t)(map_apply(maps[SM_ER2], ec + 1) * FP + map_apply(maps[SM_EF], ec + 1)) << 16;
@@ -427,7 +432,7 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
         __syncthreads();
         const __amdgpu_buffer_rsrc_t w = tile_rsrc(C + map_apply(maps[SM_RC], r0));
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < CPT; k++) {
             const float2 lo = TC[sC[k] & 0xffffu], hi = TC[sC[k] >> 16];
             const u32x4 v = {__float_as_uint(lo.x), __float_as_uint(lo.y), __float_as_uint(hi.x), __float_as_uint(hi.y)};
             __builtin_amdgcn_raw_buffer_store_b128(v, w, oC[k], 0, 0);
@@ -441,12 +446,14 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
 // k_stream_mx, for 2^kc >= 64.  A workgroup owns 64 rows (16 per wave, one
 // B matrix) and a range of 32-wide chunks of the contracted index; each chunk
 // of A ([64][32], row stride 33) and of B ([32][F], row stride F+1) is staged
-// through LDS while the next one is loaded into registers.  The chunk range's
-// partial sums go to P[split][r][f]; k_stream_lk_sum adds the splits in order.
+// through LDS while the next one is loaded into registers.  With one chunk
+// range per row group the outputs go straight to C (through LDS, coalesced);
+// otherwise each range's partial sums go to P[split][r][f] and k_stream_lk_sum
+// adds the ranges in order.
 template <int NC>
 __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
-                                                   float2 *__restrict__ P, const BitMap *__restrict__ maps, int nr,
-                                                   int kc, int nf, int ks) {
+                                                   float2 *__restrict__ P, float2 *__restrict__ C,
+                                                   const BitMap *__restrict__ maps, int nr, int kc, int nf, int ks) {
     constexpr int KP = 33, NT = 16;
     __shared__ float2 TA[64 * KP];
     __shared__ float2 TB[32 * 33];
@@ -512,6 +519,25 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
         }
         __syncthreads();
     }
+    if (ks == 0) {
+        // one chunk range: the 64 x F outputs go to C through LDS ([row][f],
+        // row stride F+1, in TA's space), written in C's memory order
+        float *Tf = reinterpret_cast<float *>(TA);
+#pragma unroll
+        for (int cb = 0; cb < NC; cb++) {
+            const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
+            if (f < F) {
+#pragma unroll
+                for (int v = 0; v < 4; v++) Tf[2 * ((16 * wave + 4 * g + v) * FP + f) + d] = acc[cb][v];
+            }
+        }
+        __syncthreads();
+        float2 *cb = C + map_apply(maps[SM_RC], r0);
+        const int nC = 64 << nf;
+        for (int e = tid; e < nC; e += 256)
+            cb[map_apply(maps[SM_EC], e)] = TA[map_apply(maps[SM_ER2], e) * FP + map_apply(maps[SM_EF], e)];
+        return;
+    }
     float *Pf = reinterpret_cast<float *>(P);
     const int64_t pbase = ((int64_t)sp << (nr + nf)) + ((r0 + 16 * wave + 4 * g) << nf);
 #pragma unroll
@@ -572,14 +598,15 @@ void launch_stream_mx(const StreamOp &op, const BitMap *d_maps, const float2 *a,
                       hipStream_t s) {
     if (op.nf <= 3) launch_stream_mx_nc<KC, 1>(op, d_maps, a, b, c, s);
     else if (op.nf == 4) launch_stream_mx_nc<KC, 2>(op, d_maps, a, b, c, s);
-    else launch_stream_mx_nc<KC, 4>(op, d_maps, a, b, c, s);
+    else if (op.nf == 5) launch_stream_mx_nc<KC, 4>(op, d_maps, a, b, c, s);
+    else launch_stream_mx_nc<KC, 8>(op, d_maps, a, b, c, s);
 }
 
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
                    float2 *w, hipStream_t s) {
     if (op.mx) {
-        if (op.tile_l < 6 || op.tile_l > 8 || op.tile_l + op.kc > 11 || op.tile_l + op.nf > 11 || op.kc > 5 ||
-            op.nf > 5 || op.nr < op.tile_l)
+        if (op.tile_l < 6 || op.tile_l > 8 || op.tile_l + op.kc > 11 || op.tile_l + op.nf > (op.nf == 6 ? 12 : 11) ||
+            op.kc > 5 || op.nf > 6 || op.nr < op.tile_l)
             fail(RQC_EPLAN, "matrix-core streaming tile exceeds the kernel's limits");
         switch (op.kc) {
         case 0: launch_stream_mx<0>(op, d_maps, a, b, c, s); break;
@@ -592,20 +619,22 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
         return;
     }
     if (op.lk) {
-        if (op.kc < 6 || op.nf > 5 || op.nr < 6 || op.lk_split < 0 || op.lk_split > op.kc - 5 || !w)
+        if (op.kc < 6 || op.nf > 5 || op.nr < 6 || op.lk_split < 0 || op.lk_split > op.kc - 5 || (op.lk_split && !w))
             fail(RQC_EPLAN, "long streaming contraction exceeds the kernel's limits");
         const int64_t blocks = (int64_t)1 << (op.nr - 6 + op.lk_split);
         if (blocks > (int64_t)1 << 30) fail(RQC_EPLAN, "long streaming contraction grid too large");
         const dim3 g((unsigned)blocks), t(256);
         if (op.nf <= 3)
-            hipLaunchKernelGGL((k_stream_lk<1>), g, t, 0, s, a, b, w, d_maps, op.nr, op.kc, op.nf, op.lk_split);
+            hipLaunchKernelGGL((k_stream_lk<1>), g, t, 0, s, a, b, w, c, d_maps, op.nr, op.kc, op.nf, op.lk_split);
         else if (op.nf == 4)
-            hipLaunchKernelGGL((k_stream_lk<2>), g, t, 0, s, a, b, w, d_maps, op.nr, op.kc, op.nf, op.lk_split);
+            hipLaunchKernelGGL((k_stream_lk<2>), g, t, 0, s, a, b, w, c, d_maps, op.nr, op.kc, op.nf, op.lk_split);
         else
-            hipLaunchKernelGGL((k_stream_lk<4>), g, t, 0, s, a, b, w, d_maps, op.nr, op.kc, op.nf, op.lk_split);
-        const int64_t n = (int64_t)1 << (op.nr + op.nf);
-        const dim3 g2((unsigned)std::min<int64_t>((n + 255) / 256, 256 * 16));
-        hipLaunchKernelGGL(k_stream_lk_sum, g2, t, 0, s, w, c, d_maps, op.nr, op.nf, op.lk_split);
+            hipLaunchKernelGGL((k_stream_lk<4>), g, t, 0, s, a, b, w, c, d_maps, op.nr, op.kc, op.nf, op.lk_split);
+        if (op.lk_split > 0) {
+            const int64_t n = (int64_t)1 << (op.nr + op.nf);
+            const dim3 g2((unsigned)std::min<int64_t>((n + 255) / 256, 256 * 16));
+            hipLaunchKernelGGL(k_stream_lk_sum, g2, t, 0, s, w, c, d_maps, op.nr, op.nf, op.lk_split);
+        }
         return;
     }
     if (op.tile_l < 0 && op.kc >= 6 && op.nf <= 4) {

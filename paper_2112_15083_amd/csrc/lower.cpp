@@ -361,7 +361,9 @@ struct Lowerer {
         // kept legs go lowest first by their lower position in A or C, so that a
         // tile's reads and writes both run over the low positions of their
         // tensors even when C's layout does not follow A's.
-        const int L = (op.kc <= 5 && op.nf <= 10) ? std::min({op.nr, 11 - std::max(op.kc, op.nf), 8}) : 0;
+        // (six new legs: tiles of 2^12 C elements and 64 rows, matrix-core form only)
+        const int L = op.kc <= 5 && op.nf == 6 && op.nr >= 6 ? 6
+                      : (op.kc <= 5 && op.nf <= 10) ? std::min({op.nr, 11 - std::max(op.kc, op.nf), 8}) : 0;
         if (L > 0) {
             std::stable_sort(rest.begin(), rest.end(), [&](int x, int y) {
                 const int kx = std::min(pos_in(LA, LC[x]), x), ky = std::min(pos_in(LA, LC[y]), y);
@@ -372,20 +374,26 @@ struct Lowerer {
         // quarter tile (one wave's rows) shares one B matrix, then the other
         // batch legs, so that a workgroup's successive tiles share one too.
         auto is_batch = [&](int j) { return pos_in(LB, LC[j]) >= 0; };
-        if (L >= 6 && op.kc <= 5 && op.nf <= 5) {
+        // At most two batch legs fit a tile (they are its top row bits); further
+        // ones are passed over for the next non-batch legs, which costs some
+        // contiguity of the tile but keeps the step on the matrix cores.
+        if (L >= 6 && op.kc <= 5 && op.nf <= 6) {
+            std::vector<int> tile;
             int nbt = 0;
-            for (int i = 0; i < L; i++) nbt += is_batch(rest[i]);
-            if (nbt <= 2) {
+            for (size_t i = 0; i < rest.size() && (int)tile.size() < L; i++)
+                if (!is_batch(rest[i]) || nbt < 2) tile.push_back(rest[i]), nbt += is_batch(rest[i]);
+            if ((int)tile.size() == L) {
                 op.mx = 1;
                 std::vector<int> r2;
-                for (int i = 0; i < L; i++)
-                    if (!is_batch(rest[i])) r2.push_back(rest[i]);
-                for (int i = 0; i < L; i++)
-                    if (is_batch(rest[i])) r2.push_back(rest[i]);
-                for (size_t i = L; i < rest.size(); i++)
-                    if (is_batch(rest[i])) r2.push_back(rest[i]);
-                for (size_t i = L; i < rest.size(); i++)
-                    if (!is_batch(rest[i])) r2.push_back(rest[i]);
+                for (int j : tile)
+                    if (!is_batch(j)) r2.push_back(j);
+                for (int j : tile)
+                    if (is_batch(j)) r2.push_back(j);
+                auto in_tile = [&](int j) { return std::find(tile.begin(), tile.end(), j) != tile.end(); };
+                for (int j : rest)
+                    if (!in_tile(j) && is_batch(j)) r2.push_back(j);
+                for (int j : rest)
+                    if (!in_tile(j) && !is_batch(j)) r2.push_back(j);
                 rest = r2;
             }
         }
@@ -443,10 +451,24 @@ struct Lowerer {
             op.m[SM_EB] = make_map(PB);
             op.m[SM_BY] = make_map(bY);
             op.m[SM_BF] = make_map(bF);
+            // unsplit: the workgroup's 64 x 2^nf outputs go to C through LDS, in
+            // C's memory order (tile element -> C offset, row, new index)
+            std::vector<int> PC;
+            for (int i = 0; i < 6; i++) PC.push_back(rcm[i]);
+            for (int v : fc) PC.push_back(v);
+            std::sort(PC.begin(), PC.end());
+            std::vector<int> er2(PC.size(), -1), ef(PC.size(), -1);
+            for (int i = 0; i < 6; i++) er2[idx(PC, rcm[i])] = i;
+            for (size_t j = 0; j < fc.size(); j++) ef[idx(PC, fc[j])] = (int)j;
+            op.m[SM_EC] = make_map(PC);
+            op.m[SM_ER2] = make_map(er2);
+            op.m[SM_EF] = make_map(ef);
             // about 2048 workgroups: 2^(nr-6) row groups times the chunk splits
             op.lk_split = std::max(0, std::min(op.kc - 5, 11 - (op.nr - 6)));
-            op.w.kind = 0;
-            op.w.off = new_alloc((int64_t)1 << (op.lk_split + op.nr + op.nf), -1);
+            if (op.lk_split > 0) {
+                op.w.kind = 0;
+                op.w.off = new_alloc((int64_t)1 << (op.lk_split + op.nr + op.nf), -1);
+            }
         }
         // LDS tiling when both the contracted and the new-leg dimensions are
         // short: tiles hold at most 2^11 elements of A and of C, and at most 256
@@ -490,6 +512,7 @@ struct Lowerer {
                 if (PA[0] != 0 || PC[0] != 0 || spanA >= ((int64_t)1 << 29) || spanC >= ((int64_t)1 << 29))
                     op.mx = 0;
             }
+            if (!op.mx && L + op.nf > 11) op.tile_l = -1; // too large for the vector tile kernel
         }
         double f = 8.0 * std::exp2((double)(LC.size() + con.size()));
         double by_ = 8.0 * (double)(size_of(a) + size_of(b) + size_of(t));
@@ -759,7 +782,7 @@ struct Lowerer {
             if (s.c_kind == 2) s.c_off = allocs[s.c_off].off; // cache offsets (kind 3) are final
         for (auto &s : prog.streams) {
             fix(s.a), fix(s.b), fix(s.c);
-            if (s.lk) fix(s.w);
+            if (s.lk && s.lk_split > 0) fix(s.w);
         }
         for (auto &p : prog.permutes) fix(p.src), fix(p.dst);
         for (auto &g : prog.gemms) {

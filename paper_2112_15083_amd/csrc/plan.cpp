@@ -130,9 +130,21 @@ double estimate_seconds(const PlanCore &p) {
     double t = 20e-6;
     for (const Op &op : pg.ops) {
         double dt;
-        if (op.kind == OP_GEMM) dt = std::max(op.flops / gemm_rate, op.bytes / 5.5e12) + 4e-6;
-        else if (op.kind == OP_SMALL) dt = 70e-6;
-        else dt = op.bytes / 4.5e12 + 4e-6;
+        if (op.kind == OP_GEMM) {
+            dt = std::max(op.flops / gemm_rate, op.bytes / 5.5e12) + 4e-6;
+        } else if (op.kind == OP_SMALL) {
+            dt = 70e-6;
+        } else if (op.kind == OP_PERMUTE) {
+            dt = op.bytes / 5e12 + 4e-6;
+        } else {
+            // streaming kernels at their measured rates: matrix-core tiles
+            // ~4.5 TB/s, long contractions ~2 TB/s plus their partial-sum pass,
+            // the vector fallbacks under 1 TB/s
+            const StreamOp &so = pg.streams[op.index];
+            const double rate = so.mx ? 4.5e12 : (so.lk ? 2e12 : 0.8e12);
+            dt = op.bytes / rate + 4e-6;
+            if (so.lk && so.lk_split > 0) dt += 16.0 * std::exp2((double)(so.lk_split + so.nr + so.nf)) / 2e12 + 4e-6;
+        }
         t += (op.kind == OP_SMALL || op.dep) ? dt : w_indep * dt;
     }
     return t * (double)std::max<int64_t>(1, p.info.n_groups);
@@ -178,12 +190,11 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
         std::vector<SearchResult> rs = search_tree(path_legs, nv, kept, sp.forbidden, user_sliced,
                                                    p.opts.max_log2_tensor, p.opts.n_sliced_target, trials,
                                                    p.opts.path_seed);
-        // the few best by the proxy cost are lowered and compared by estimated
-        // time (more of them with the global cache, whose per-batch cost the
-        // proxy does not see)
+        // the best by the proxy cost are lowered and compared by estimated time
+        // (with the global cache, the per-batch time the proxy does not see)
         size_t best = 0;
         double best_t = 1e300;
-        const size_t n_lower = p.opts.global_cache ? 32 : 8;
+        const size_t n_lower = 64; // lowering a candidate costs ~10 ms
         for (size_t i = 0; i < rs.size() && i < n_lower; i++) {
             PlanCore q;
             q.opts = p.opts;
@@ -430,6 +441,7 @@ void plan_finish(PlanCore &p) {
         I.cache_bytes = (int64_t)bytes;
         I.flops_cached = pg.flops_indep * (double)I.n_groups;
     }
+    I.est_seconds = estimate_seconds(p);
 }
 
 } // namespace rqc

@@ -292,7 +292,7 @@ float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hi
             const StreamOp &so = pg.streams[op.index];
             Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
             launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c),
-                          so.lk ? ptr(so.w) : nullptr, s);
+                          so.lk && so.lk_split > 0 ? ptr(so.w) : nullptr, s);
             break;
         }
         case OP_PERMUTE: {

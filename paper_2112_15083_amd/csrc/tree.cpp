@@ -8,6 +8,7 @@
 // one at a time, each chosen to minimise the total sliced cost among the legs
 // of the largest tensors (or among all legs once the memory target holds).
 #include <algorithm>
+#include <numeric>
 #include <atomic>
 #include <functional>
 #include <thread>
@@ -428,34 +429,51 @@ Tree reconfigure_tree(const Tree &t, const std::vector<Legs> &leaf_legs, int n_v
     return out;
 }
 
+// Two phases: `trials` randomised greedy trees are built and scored by the
+// time-like cost of the unsliced tree (cheap); the best sixteenth of them (at
+// least 8) are rebuilt from their seeds, re-optimised by subtree
+// reconfiguration (the expensive part) and sliced, and scored again.
 std::vector<SearchResult> search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
                                       const std::vector<char> &forbidden, const std::vector<int> *user_sliced,
                                       int max_log2_tensor, int n_target, int trials, uint64_t seed) {
-    std::vector<SearchResult> res(trials);
     std::vector<char> none(n_vars, 0);
-    auto run = [&](int tr) {
+    auto greedy = [&](int tr) {
         std::mt19937_64 rng(seed * 0x9E3779B97F4A7C15ull + (uint64_t)tr);
         std::uniform_real_distribution<double> U(0.0, 1.0);
         double temp = tr == 0 ? 0.0 : 0.05 + 0.95 * U(rng);
         double costmod = tr == 0 ? 1.0 : 0.5 + 1.5 * U(rng);
-        Tree t = greedy_tree(leaf_legs, n_vars, kept, rng(), temp, costmod);
-        t = reconfigure_tree(t, leaf_legs, n_vars, kept, 8, 3);
+        return greedy_tree(leaf_legs, n_vars, kept, rng(), temp, costmod);
+    };
+    const int nth = (int)std::max(1u, std::min<unsigned>(16u, std::thread::hardware_concurrency()));
+    auto parallel = [&](int n, const std::function<void(int)> &fn) {
+        std::atomic<int> next{0};
+        std::vector<std::thread> pool;
+        for (int i = 0; i < std::min(nth, n); i++)
+            pool.emplace_back([&] {
+                for (int k = next++; k < n; k = next++) fn(k);
+            });
+        for (auto &th : pool) th.join();
+    };
+    std::vector<double> score(trials);
+    parallel(trials, [&](int tr) {
+        Tree t = greedy(tr);
+        score[tr] = tree_log2_time_cost(t, tree_legs(t, leaf_legs, n_vars, none, kept));
+    });
+    std::vector<int> order(trials);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return score[x] < score[y]; });
+    const int keep = std::min(trials, std::max(8, trials / 16));
+    std::vector<SearchResult> res(keep);
+    parallel(keep, [&](int i) {
+        Tree t = reconfigure_tree(greedy(order[i]), leaf_legs, n_vars, kept, 8, 3);
         auto legs = tree_legs(t, leaf_legs, n_vars, none, kept);
         std::vector<int> sl =
             user_sliced ? *user_sliced : greedy_slice(t, legs, n_vars, forbidden, max_log2_tensor, n_target);
         std::vector<char> rem(n_vars, 0);
         for (int v : sl) rem[v] = 1;
         auto legs2 = tree_legs(t, leaf_legs, n_vars, rem, kept);
-        res[tr] = {t, sl, tree_log2_time_cost(t, legs2) + (double)sl.size()};
-    };
-    int nth = (int)std::max(1u, std::min<unsigned>(16u, std::thread::hardware_concurrency()));
-    std::atomic<int> next{0};
-    std::vector<std::thread> pool;
-    for (int i = 0; i < std::min(nth, trials); i++)
-        pool.emplace_back([&] {
-            for (int tr = next++; tr < trials; tr = next++) run(tr);
-        });
-    for (auto &th : pool) th.join();
+        res[i] = {t, sl, tree_log2_time_cost(t, legs2) + (double)sl.size()};
+    });
     std::stable_sort(res.begin(), res.end(),
                      [](const SearchResult &a, const SearchResult &b) { return a.log2cost < b.log2cost; });
     return res;

@@ -49,7 +49,8 @@ class PlanInfo(ctypes.Structure):
                 ("max_log2_tensor", ctypes.c_int32), ("n_steps", ctypes.c_int32),
                 ("n_launches", ctypes.c_int32), ("n_groups", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
-                ("cache_bytes", ctypes.c_int64), ("flops_cached", ctypes.c_double)]
+                ("cache_bytes", ctypes.c_int64), ("flops_cached", ctypes.c_double),
+                ("est_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
