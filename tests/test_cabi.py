@@ -80,10 +80,12 @@ def test_global_cache_plan_report(rqc):
     assert info["cache_bytes"] == 2 * 8 * 2 ** 12  # the final 2^12 tensor, one group + spare
     t = synthetic.circuit_text(4, 4, 10, 1)
     c = rqc.load_circuit(t)
-    plain = rqc.plan_info(rqc.plan_create(c, list(range(10, 16)), dry_run=1, n_sliced_target=3,
-                                          max_log2_batched=1, path_seed=1))
-    info = rqc.plan_info(rqc.plan_create(c, list(range(10, 16)), dry_run=1, n_sliced_target=3,
-                                         max_log2_batched=1, path_seed=1, global_cache=1))
+    cached = rqc.plan_create(c, list(range(10, 16)), dry_run=1, n_sliced_target=3, max_log2_batched=1,
+                             path_seed=1, global_cache=1)
+    info = rqc.plan_info(cached)
+    # the same tree without the cache (the planner's own choice differs with it)
+    plain = rqc.plan_info(rqc.plan_create(c, list(range(10, 16)), dry_run=1, path=rqc.plan_path(cached),
+                                          sliced_legs=rqc.plan_sliced_legs(cached), max_log2_batched=1))
     assert plain["cache_bytes"] == 0 and plain["flops_cached"] == 0
     assert 0 < info["flops_cached"] < info["flops_per_batch"] == plain["flops_per_batch"]
     assert info["cache_bytes"] % (8 * (info["n_groups"] + 1)) == 0
