@@ -18,6 +18,10 @@ Workloads:
                  timed on a prefix of the slice list and extrapolated (labelled)
   --serve        the serving loop on a Poisson stream of synthetic requests
   --copy-calibration  a plain 1 GiB device copy, for scaling HBM counters
+
+Plans come from a 65536-trial tree search whose 4 best estimated trees are
+timed on the GPU (--path-trials, --autotune); planning is reported separately
+(plan_seconds) and is not part of a step.
 """
 from __future__ import annotations
 
@@ -118,7 +122,7 @@ def run_mid_like(args, rqc, torch):
         partial = dict(target_fidelity=args.target_fidelity)
     n_sliced = args.partial_sliced if args.target_fidelity else N_SLICED[args.config]
     plan = rqc.plan_create(circ, open_q, n_sliced_target=n_sliced, path_trials=args.path_trials,
-                           path_seed=args.path_seed, precision=prec, profile=1, **partial)
+                           path_seed=args.path_seed, precision=prec, profile=1, autotune=args.autotune, **partial)
     plan_s = time.perf_counter() - t0
     info = rqc.plan_info(plan)
     stream = torch.cuda.current_stream()
@@ -205,7 +209,7 @@ def run_mid_like(args, rqc, torch):
         # and every batch then contracts only the rest.  Reported beside the
         # headline value, which recomputes everything on every step.
         cplan = rqc.plan_create(circ, open_q, n_sliced_target=n_sliced, path_trials=args.path_trials,
-                                path_seed=args.path_seed, precision=prec, global_cache=1)
+                                path_seed=args.path_seed, precision=prec, global_cache=1, autotune=args.autotune)
         cinfo = rqc.plan_info(cplan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -347,8 +351,11 @@ def main():
     ap.add_argument("--config", default="mid", choices=["tiny", "mid", "precision", "large"])
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--path-trials", type=int, default=256)
+    ap.add_argument("--path-trials", type=int, default=None,
+                    help="randomised greedy trials of the tree search (default 65536; 4096 for large, 256 for tiny)")
     ap.add_argument("--path-seed", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=4,
+                    help="time this many of the best estimated trees on the GPU and keep the fastest")
     ap.add_argument("--large-prefix", type=int, default=16)
     ap.add_argument("--target-fidelity", type=float, default=0.0)
     ap.add_argument("--partial-sliced", type=int, default=12)
@@ -358,6 +365,8 @@ def main():
     ap.add_argument("--no-global-cache", dest="global_cache", action="store_false",
                     help="skip the global-cache measurement reported beside the headline value")
     args = ap.parse_args()
+    if args.path_trials is None:
+        args.path_trials = {"tiny": 256, "large": 4096}.get(args.config, 65536)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sliced contraction would shard "
               "by slice range across GPUs, which this build does not run.", file=sys.stderr)

@@ -120,6 +120,11 @@ typedef struct {
        cache.  Costs rqc_plan_info_t.cache_bytes of workspace (RQC_EPLAN if that
        exceeds 128 GiB). */
     int32_t global_cache;
+    /* > 1: time this many of the searched trees (best estimated time first) on
+       the device, one batch each after a warm-up, and keep the fastest; the
+       planner's estimate alone decides otherwise.  Only for searched trees
+       with full slicing. */
+    int32_t autotune;
 } rqc_plan_opts;
 
 typedef struct {

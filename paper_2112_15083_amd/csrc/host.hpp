@@ -270,6 +270,13 @@ struct PlanCore {
     std::vector<LeafSel> sel;
     std::vector<cf> full;                      // leaf store
     rqc_plan_info_t info{};
+    // searched trees, best estimated time first (for timing on the device)
+    struct Candidate {
+        Tree tree;
+        std::vector<int> sliced;
+        double est;
+    };
+    std::vector<Candidate> candidates;
 };
 
 // Contraction tree and sliced legs (user path/legs or the randomised search).

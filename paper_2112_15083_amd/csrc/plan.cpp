@@ -192,9 +192,8 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
                                                    p.opts.path_seed);
         // the best by the proxy cost are lowered and compared by estimated time
         // (with the global cache, the per-batch time the proxy does not see)
-        size_t best = 0;
-        double best_t = 1e300;
         const size_t n_lower = 64; // lowering a candidate costs ~10 ms
+        p.candidates.clear();
         for (size_t i = 0; i < rs.size() && i < n_lower; i++) {
             PlanCore q;
             q.opts = p.opts;
@@ -202,17 +201,17 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
             q.tree = rs[i].tree;
             q.sliced = rs[i].sliced;
             q.user_legs = p.user_legs;
-            double t;
             try {
                 plan_finish(q);
-                t = estimate_seconds(q);
+                p.candidates.push_back({rs[i].tree, rs[i].sliced, estimate_seconds(q)});
             } catch (const Error &) {
-                t = 1e299;
             }
-            if (t < best_t) best_t = t, best = i;
         }
-        p.tree = rs[best].tree;
-        p.sliced = rs[best].sliced;
+        if (p.candidates.empty()) fail(RQC_EPLAN, "no searched tree could be lowered");
+        std::stable_sort(p.candidates.begin(), p.candidates.end(),
+                         [](const PlanCore::Candidate &a, const PlanCore::Candidate &b) { return a.est < b.est; });
+        p.tree = p.candidates[0].tree;
+        p.sliced = p.candidates[0].sliced;
     }
     auto legs0 = tree_legs(p.tree, path_legs, nv, fixed, kept);
     p.info.flops_unsliced = 8.0 * std::exp2(tree_log2_cost_sum(p.tree, legs0));

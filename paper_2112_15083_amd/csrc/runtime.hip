@@ -379,6 +379,46 @@ void execute(rqc_plan *p, const GroupList &groups, bool is_default, const uint64
     if (p->opts.profile && p->pending.size() > 8192) p->flush_profile();
 }
 
+// Device time of one batch on a candidate tree (after one warm-up batch, which
+// also fills a global cache), in seconds.
+double time_candidate(const PlanCore &base, const PlanCore::Candidate &cand) {
+    auto Q = std::make_unique<rqc_plan>();
+    rqc_plan &q = *Q;
+    q.opts = base.opts;
+    q.opts.profile = 0;
+    q.opts.autotune = 0;
+    q.spec = base.spec;
+    q.tree = cand.tree;
+    q.sliced = cand.sliced;
+    q.user_legs = base.user_legs;
+    HIP_OK(hipGetDevice(&q.device));
+    plan_finish(q);
+    q.upload();
+    const int64_t nout = (int64_t)1 << q.spec.open_vars.size();
+    float2 *amps = (float2 *)q.dalloc((size_t)nout * sizeof(float2));
+    struct Res {
+        hipStream_t s = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Res() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } r;
+    HIP_OK(hipStreamCreate(&r.s)); // default priority
+    HIP_OK(hipEventCreate(&r.a));
+    HIP_OK(hipEventCreate(&r.b));
+    const uint64_t zero = 0;
+    execute(&q, default_groups(&q), true, &zero, 1, amps, nullptr, r.s);
+    HIP_OK(hipEventRecord(r.a, r.s));
+    execute(&q, default_groups(&q), true, &zero, 1, amps, nullptr, r.s);
+    HIP_OK(hipEventRecord(r.b, r.s));
+    HIP_OK(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+    return 1e-3 * ms;
+}
+
 // R[i] = ||psi_i||^2 by contracting the doubled network on the GPU (Fig. 1).
 std::vector<double> gpu_norms(const rqc_plan_opts &outer, const NetSpec &spec, const std::vector<int> &S) {
     auto P = std::make_unique<rqc_plan>();
@@ -479,6 +519,18 @@ rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_
         std::vector<int> user;
         if (sliced_legs) user.assign(sliced_legs, sliced_legs + n_sliced);
         plan_tree(p, path, n_path_pairs, sliced_legs ? &user : nullptr);
+        // time the best candidates on the device (skipping any estimated over 2 s)
+        if (p.opts.autotune > 1 && !partial && !p.opts.dry_run && !path && p.candidates.size() > 1) {
+            size_t best = 0;
+            double best_t = 1e300;
+            for (size_t i = 0; i < p.candidates.size() && (int)i < p.opts.autotune; i++) {
+                if (p.candidates[i].est > 2.0) continue;
+                const double t = time_candidate(p, p.candidates[i]);
+                if (t < best_t) best_t = t, best = i;
+            }
+            p.tree = p.candidates[best].tree;
+            p.sliced = p.candidates[best].sliced;
+        }
         if (partial) {
             rqc_plan_opts o = p.opts;
             plan_partial(p, c->net, [&](const NetSpec &ds, const std::vector<int> &S) { return gpu_norms(o, ds, S); });

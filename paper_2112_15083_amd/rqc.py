@@ -37,7 +37,7 @@ class PlanOpts(ctypes.Structure):
                 ("path_trials", ctypes.c_int32),
                 ("path_seed", ctypes.c_uint64), ("profile", ctypes.c_int32), ("dry_run", ctypes.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
-                ("global_cache", ctypes.c_int32)]
+                ("global_cache", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
