@@ -90,6 +90,7 @@ def kernel_roofline(prof, precision_is_c64):
                 "frac": achieved / PEAK["hbm_gbs"]}
     roof.update({"kernel": cls, "launches": pc["launches"],
                  "avg_launch_us": 1e6 * pc["seconds"] / max(1, pc["launches"]),
+                 "bytes_per_launch": pc["bytes"] / max(1, pc["launches"]),
                  "traffic": measured_traffic(cls)})
     return roof
 

@@ -121,9 +121,9 @@ typedef struct {
        exceeds 128 GiB). */
     int32_t global_cache;
     /* > 1: time this many of the searched trees (best estimated time first) on
-       the device, one batch each after a warm-up, and keep the fastest; the
-       planner's estimate alone decides otherwise.  Only for searched trees
-       with full slicing. */
+       the device, one batch each after a warm-up, and keep the fastest if it
+       beats the estimate's choice by at least 5 %; the planner's estimate
+       alone decides otherwise.  Only for searched trees with full slicing. */
     int32_t autotune;
 } rqc_plan_opts;
 

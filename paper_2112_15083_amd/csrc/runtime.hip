@@ -519,11 +519,14 @@ rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_
         std::vector<int> user;
         if (sliced_legs) user.assign(sliced_legs, sliced_legs + n_sliced);
         plan_tree(p, path, n_path_pairs, sliced_legs ? &user : nullptr);
-        // time the best candidates on the device (skipping any estimated over 2 s)
-        if (p.opts.autotune > 1 && !partial && !p.opts.dry_run && !path && p.candidates.size() > 1) {
+        // time the best candidates on the device (skipping any estimated over
+        // 2 s); another tree replaces the estimate's choice only if it is at
+        // least 5 % faster, so that timing noise does not change the plan
+        if (p.opts.autotune > 1 && !partial && !p.opts.dry_run && !path && p.candidates.size() > 1 &&
+            p.candidates[0].est <= 2.0) {
             size_t best = 0;
-            double best_t = 1e300;
-            for (size_t i = 0; i < p.candidates.size() && (int)i < p.opts.autotune; i++) {
+            double best_t = 0.95 * time_candidate(p, p.candidates[0]);
+            for (size_t i = 1; i < p.candidates.size() && (int)i < p.opts.autotune; i++) {
                 if (p.candidates[i].est > 2.0) continue;
                 const double t = time_candidate(p, p.candidates[i]);
                 if (t < best_t) best_t = t, best = i;
