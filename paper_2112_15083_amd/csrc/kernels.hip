@@ -317,8 +317,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float2 *base) 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base), (short)0, -1, 0x00020000);
 }
 
+// Waves per SIMD that each instance's register budget is held to (B' takes
+// max(1, 2^(KC-1)) * NC registers per lane, the accumulators 4 * NC): four
+// wherever B', the accumulators and both A prefetch sets fit 128 registers
+// without spilling, else what the instance reaches unconstrained.
+constexpr int mx_waves(int KC, int NC) {
+    return NC == 8 ? (KC <= 1 ? 3 : KC <= 4 ? 2 : 1)
+           : KC == 5 ? (NC <= 2 ? 3 : 2)
+           : (KC >= 3 && NC == 4) ? 3 : 4;
+}
+
 template <int KC, int NC>
-__global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A, const float2 *__restrict__ B,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_waves(KC, NC)))) k_stream_mx(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                    float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
                                                    int nf, int L) {
     constexpr int K = 1 << KC, KP = K + 1;
@@ -361,18 +371,22 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
     const int64_t n_tiles = (int64_t)1 << (nr - L);
     int64_t t = blockIdx.x;
     if (t >= n_tiles) return; // whole workgroup
-    u32x4 pa[4];
-    auto load = [&](int64_t tt) {
+    // two tiles of A in flight: the workgroup's next two tiles are loaded into
+    // registers (pa0, pa1 in turn) while the current one is computed
+    u32x4 pa0[4], pa1[4];
+    const int64_t G = gridDim.x;
+    auto load = [&](u32x4 (&pa)[4], int64_t tt) {
         const __amdgpu_buffer_rsrc_t r = tile_rsrc(A + map_apply(maps[SM_RA], tt << L));
 #pragma unroll
         for (int k = 0; k < 4; k++) pa[k] = __builtin_amdgcn_raw_buffer_load_b128(r, oA[k], 0, 0);
     };
-    load(t);
-    // One tile: stage the prefetched A, load the next tile's A, multiply,
-    // store C.  The first tile is peeled off the loop so that every entry to
-    // the loop has the same loads and stores in flight (the next A, then the
-    // previous C), and the wait before staging covers only the loads.
-    auto tile = [&](int64_t t) {
+    load(pa0, t);
+    load(pa1, t + G < n_tiles ? t + G : t);
+    // One tile: stage its prefetched A, load the A two tiles ahead into the
+    // same registers, multiply, store C.  The loop is unrolled by two so that
+    // the register sets alternate statically, and the wait before staging
+    // covers only the loads of the set being staged.
+    auto tile = [&](int64_t t, u32x4 (&pa)[4]) {
         const int64_t r0 = t << L;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -401,8 +415,8 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
             __builtin_amdgcn_s_waitcnt(0x0f70); // vmcnt(0)
         }
         __syncthreads();
-        // next tile's A (the current one again after the last tile)
-        load(t + gridDim.x < n_tiles ? t + gridDim.x : t);
+        // the A two tiles ahead (the current one again, an L2 hit, past the end)
+        load(pa, t + 2 * G < n_tiles ? t + 2 * G : t);
         for (int q = 0; q < rbw; q++) {
             const int rb = wrow0 + 16 * q;
             floatx4 acc[NC];
@@ -438,8 +452,12 @@ __global__ void __launch_bounds__(256) k_stream_mx(const float2 *__restrict__ A,
             __builtin_amdgcn_raw_buffer_store_b128(v, w, oC[k], 0, 0);
         }
     };
-    tile(t);
-    for (t += gridDim.x; t < n_tiles; t += gridDim.x) tile(t);
+    for (;;) {
+        tile(t, pa0);
+        if ((t += G) >= n_tiles) break;
+        tile(t, pa1);
+        if ((t += G) >= n_tiles) break;
+    }
 }
 
 // Long contraction on matrix cores: the same real block product as

@@ -188,6 +188,7 @@ struct Lowerer {
             if (contains(C, v)) LC.push_back(v);
         for (int v : LB)
             if (contains(C, v) && pos_in(LA, v) < 0) LC.push_back(v);
+        if (c_kind != 0) LC = preferred_layout(t, LC); // a fused subtree's result
         layout[t] = LC;
         std::vector<int> con;
         for (int v : LA)
@@ -296,6 +297,72 @@ struct Lowerer {
         return b;
     }
 
+    // Legs of tensor t that its consumer keeps as batch legs (in both operands
+    // and in the result) when that consumer is a streaming step.  Streaming
+    // tiles run over non-batch legs, so t keeps these legs at its high
+    // positions and leaves its low (contiguous) positions to legs a tile covers.
+    Legs late_legs(int t) {
+        Legs out;
+        const int par = parent[t];
+        if (par < 0 || gemm_worthy(par)) return out;
+        auto [a, b] = tree.steps[par - tree.n_leaves];
+        const Legs &o = legs[a == t ? b : a], &pc = legs[par];
+        for (int v : legs[t])
+            if (contains(o, v) && contains(pc, v)) out.push_back(v);
+        return out;
+    }
+    static std::vector<int> late_last(std::vector<int> v, const Legs &late) {
+        std::stable_partition(v.begin(), v.end(), [&](int x) { return !contains(late, x); });
+        return v;
+    }
+
+    // Layout of a computed tensor whose natural layout is LC.  With a GEMM
+    // consumer: one of that GEMM's operand layouts (A: [K | M | batch] or
+    // [M | K | batch], B: [N | K | batch] or [K | N | batch]), so no permute is
+    // needed.  The contracted and batch groups stay ascending (the other
+    // operand uses the same orders); the free group follows LC, with the legs
+    // that the GEMM's own streaming consumer batches over last; and the
+    // free-group-first form is taken when its low legs agree better with LC's,
+    // which keeps the producing step's reads and writes contiguous together.
+    // Otherwise LC with the consumer's batch legs last.
+    std::vector<int> preferred_layout(int t, const std::vector<int> &LC) {
+        const int par = parent[t];
+        if (par >= 0 && gemm_worthy(par)) {
+            auto [pa, pb] = tree.steps[par - tree.n_leaves];
+            const Legs &PA = legs[pa], &PB = legs[pb], &PC = legs[par];
+            Legs bt, cn, fa_, fb_;
+            for (int v : PA) {
+                bool inb = contains(PB, v), inc = contains(PC, v);
+                if (inb && inc) bt.push_back(v);
+                else if (inb) cn.push_back(v);
+                else fa_.push_back(v);
+            }
+            for (int v : PB)
+                if (!contains(PA, v)) fb_.push_back(v);
+            std::vector<int> fr(t == pa ? fa_ : fb_);
+            std::stable_sort(fr.begin(), fr.end(), [&](int x, int y) { return pos_in(LC, x) < pos_in(LC, y); });
+            fr = late_last(fr, late_legs(par));
+            std::vector<int> kf = cn, ff = fr; // contracted group first / free group first
+            kf.insert(kf.end(), fr.begin(), fr.end());
+            ff.insert(ff.end(), cn.begin(), cn.end());
+            kf.insert(kf.end(), bt.begin(), bt.end());
+            ff.insert(ff.end(), bt.begin(), bt.end());
+            if (set_of(kf) != legs[t]) return LC;
+            // low legs shared with LC (a streaming tile spans at most 11 bits)
+            const size_t T = std::min<size_t>(11, LC.size());
+            auto agree = [&](const std::vector<int> &W) {
+                int n = 0;
+                for (size_t j = 0; j < T; j++)
+                    n += std::find(LC.begin(), LC.begin() + T, W[j]) != LC.begin() + T;
+                return n;
+            };
+            // B's default is free group first ([N | K]), A's contracted first
+            const bool free_first = t == pa ? agree(ff) > agree(kf) : agree(ff) >= agree(kf);
+            return free_first ? ff : kf;
+        }
+        return late_last(LC, late_legs(t));
+    }
+
     void emit_stream(int t) {
         auto [a, b] = tree.steps[t - tree.n_leaves];
         if (size_of(b) > size_of(a)) std::swap(a, b);
@@ -316,33 +383,7 @@ struct Lowerer {
             }
         }
         for (; nb < newb.size(); nb++) LC.push_back(newb[nb]);
-        // If the consumer is a GEMM, write the result directly in that GEMM's
-        // canonical operand layout (A: [K | M | batch], B: [N | K | batch], legs
-        // ascending within groups) so it needs no permute.
-        const int par = parent[t];
-        if (par >= 0 && gemm_worthy(par)) {
-            auto [pa, pb] = tree.steps[par - tree.n_leaves];
-            const Legs &PA = legs[pa], &PB = legs[pb], &PC = legs[par];
-            Legs bt, cn, fa_, fb_;
-            for (int v : PA) {
-                bool inb = contains(PB, v), inc = contains(PC, v);
-                if (inb && inc) bt.push_back(v);
-                else if (inb) cn.push_back(v);
-                else fa_.push_back(v);
-            }
-            for (int v : PB)
-                if (!contains(PA, v)) fb_.push_back(v);
-            std::vector<int> want;
-            if (t == pa) {
-                want = cn;
-                want.insert(want.end(), fa_.begin(), fa_.end());
-            } else {
-                want = fb_;
-                want.insert(want.end(), cn.begin(), cn.end());
-            }
-            want.insert(want.end(), bt.begin(), bt.end());
-            if (set_of(want) == C) LC = want;
-        }
+        LC = preferred_layout(t, LC);
         layout[t] = LC;
         StreamOp op;
         op.a = buf_of(a);
@@ -580,6 +621,13 @@ struct Lowerer {
         bord = ordered_subset(LA, batch);
         faord = ordered_subset(LA, fa);
         fbord = ordered_subset(LB, fb);
+        // C's lowest legs are B's free legs: those a streaming consumer batches
+        // over go last, permuting B for it when B is small
+        bool fb_moved = false;
+        if (const Legs late = late_legs(t); !late.empty()) {
+            std::vector<int> w = late_last(fbord, late);
+            if (w != fbord && size_of(b) <= ((int64_t)1 << 24)) fbord = w, fb_moved = true;
+        }
         // B view with A's K and batch orders
         auto b_layout = [&](int nfast) {
             std::vector<int> L;
@@ -598,7 +646,7 @@ struct Lowerer {
         else if (LB == b_layout(0)) b_nfast = 0;
         // If B fits its own groups but in a different K/batch order, consider
         // permuting A to B's orders instead when A is the smaller tensor.
-        if (b_nfast < 0 && size_of(a) < size_of(b)) {
+        if (b_nfast < 0 && !fb_moved && size_of(a) < size_of(b)) {
             bool bk = fits3(LB, fb, con, batch), bn = fits3(LB, con, fb, batch);
             if (bk || bn) {
                 kord = ordered_subset(LB, con);

@@ -232,6 +232,16 @@ void dump_plan(const rqc_plan &p) {
             std::fprintf(stderr, "  stream %s rc=%d kc=%d nr=%d nf=%d tile=%d batch=%d/%d flops=%.3g bytes=%.3g\n",
                          so.mx ? "mx" : (so.lk ? "lk" : "vec"), so.rc, so.kc, so.nr, so.nf, so.tile_l, nbat_tile, nbat,
                          op.flops, op.bytes);
+            if (so.mx || so.lk) {
+                // memory bits of A that a tile covers (bit 0 missing = pairs not contiguous)
+                for (int which : {SM_EA, SM_EC}) {
+                    std::fprintf(stderr, "    tile %s bits:", which == SM_EA ? "A" : "C");
+                    const BitMap &e = so.m[which];
+                    for (int i = 0; i < e.n; i++)
+                        for (int j = 0; j < e.len(i); j++) std::fprintf(stderr, " %d", e.dst(i) + j);
+                    std::fprintf(stderr, "\n");
+                }
+            }
         } else if (op.kind == OP_GEMM) {
             const GemmOp &g = pg.gemms[op.index];
             std::fprintf(stderr, "  gemm b=%lld M=%lld N=%lld K=%lld ak=%d bn=%d ks=%d flops=%.3g\n", (long long)g.batch,
