@@ -331,11 +331,16 @@ template <int KC, int NC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_waves(KC, NC)))) k_stream_mx(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                    float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
                                                    int nf, int L) {
-    constexpr int K = 1 << KC, KP = K + 1;
+    // A rows hold (re, im) per y as floats at a stride of RSA = 4 * odd floats,
+    // so a wave's operand reads (16 rows by 4 consecutive floats) hit 64
+    // distinct banks; C rows hold F complex at a stride of F + 2, so the 4 rows
+    // a wave writes per accumulator register start 16 banks apart.
+    constexpr int K = 1 << KC, RSA = (K >= 4 ? 2 * K : 8) + 4, KP = RSA / 2;
     constexpr int NT = K >= 2 ? K / 2 : 1; // 4-deep real k steps: 2K / 4
     extern __shared__ float2 lds[];
-    const int R = 1 << L, F = 1 << nf, FP = F + 1;
+    const int R = 1 << L, F = 1 << nf, FP = F + 2;
     float2 *TA = lds;
+    const float *TAf = reinterpret_cast<const float *>(lds);
     float2 *TC = lds + R * KP;
     float *TCf = reinterpret_cast<float *>(TC);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -422,14 +427,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_wav
             floatx4 acc[NC];
 #pragma unroll
             for (int cb = 0; cb < NC; cb++) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const float2 *arow = TA + (rb + col) * KP + (g >> 1);
+            const float *arow = TAf + (rb + col) * RSA + g; // A[row][k' = 4s + g]
 #pragma unroll
             for (int s = 0; s < NT; s++) {
                 float a = 0.f;
-                if (K >= 2 || (g >> 1) == 0) {
-                    const float2 x = arow[2 * s];
-                    a = cpart ? x.y : x.x;
-                }
+                if (K >= 2 || (g >> 1) == 0) a = arow[4 * s];
 #pragma unroll
                 for (int cb = 0; cb < NC; cb++)
                     acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq[s][cb], acc[cb], 0, 0, 0);
@@ -462,22 +464,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_wav
 
 // Long contraction on matrix cores: the same real block product as
 // k_stream_mx, for 2^kc >= 64.  A workgroup owns 64 rows (16 per wave, one
-// B matrix) and a range of 32-wide chunks of the contracted index; each chunk
-// of A ([64][32], row stride 33) and of B ([32][F], row stride F+1) is staged
-// through LDS while the next one is loaded into registers.  With one chunk
-// range per row group the outputs go straight to C (through LDS, coalesced);
-// otherwise each range's partial sums go to P[split][r][f] and k_stream_lk_sum
-// adds the ranges in order.
+// B matrix) and a range of 32-wide chunks of the contracted index.  Each chunk
+// is staged through LDS while the next one is loaded into registers: A as
+// floats ([row][2y + c], row stride 68, so that a wave's operand reads -- 16
+// rows by 4 consecutive floats -- fall in 64 distinct banks) and B already in
+// its real block form B'[2y + c][2f + d] (row stride SB = 16 mod 64, so that
+// the 4 rows a read spans use disjoint banks), which makes every matrix-core
+// operand one 32-bit LDS read.  With one chunk range per row group the
+// outputs go straight to C (through LDS, coalesced); otherwise each range's
+// partial sums go to P[split][r][f] and k_stream_lk_sum adds the ranges in
+// order.
 template <int NC>
 __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                    float2 *__restrict__ P, float2 *__restrict__ C,
                                                    const BitMap *__restrict__ maps, int nr, int kc, int nf, int ks) {
-    constexpr int KP = 33, NT = 16;
-    __shared__ float2 TA[64 * KP];
-    __shared__ float2 TB[32 * 33];
-    const int F = 1 << nf, FP = F + 1, nBt = 32 << nf;
+    constexpr int RS = 68, SB = NC == 1 ? 16 : 16 * NC + 16, NT = 16;
+    __shared__ float TA[64 * RS];
+    __shared__ float TB[64 * SB];
+    const int F = 1 << nf, nBt = 32 << nf;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = lane >> 4, col = lane & 15, cpart = g & 1;
+    const int g = lane >> 4, col = lane & 15;
     const int64_t gi = (int64_t)blockIdx.x >> ks;
     const int sp = blockIdx.x & ((1 << ks) - 1);
     const int nch = 1 << (kc - 5 - ks), c0 = sp * nch;
@@ -487,14 +493,16 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
     for (int k = 0; k < 8; k++) {
         const int e = tid + 256 * k;
         offA[k] = (int)map_apply(maps[SM_EA], e);
-        sA[k] = (int)map_apply(maps[SM_ER], e) * KP + (int)map_apply(maps[SM_EY], e);
+        sA[k] = (int)map_apply(maps[SM_ER], e) * RS + 2 * (int)map_apply(maps[SM_EY], e);
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int e = tid + 256 * k;
         offB[k] = e < nBt ? (int)map_apply(maps[SM_EB], e) : 0;
-        sB[k] = e < nBt ? (int)map_apply(maps[SM_BY], e) * FP + (int)map_apply(maps[SM_BF], e) : 0;
+        sB[k] = e < nBt ? 2 * (int)map_apply(maps[SM_BY], e) * SB + 2 * (int)map_apply(maps[SM_BF], e) : 0;
     }
+    // B' columns 2f + d with f >= F (fewer than 8 new indices) stay zero
+    for (int i = tid; i < 64 * SB; i += 256) TB[i] = 0.f;
     const int64_t abase = map_apply(maps[SM_RA], r0), bbase = map_apply(maps[SM_RB], r0);
     float2 pa[8], pb[4];
     auto load = [&](int ch) {
@@ -510,50 +518,48 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
 #pragma unroll
     for (int cb = 0; cb < NC; cb++) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
     load(c0);
-    const float2 *arow = TA + (16 * wave + col) * KP + (g >> 1);
+    __syncthreads(); // the zero fill of B' before its first staging
+    // this lane's operands: A[row][k' = 4s + g], B'[k' = 4s + g][col + 16 cb]
+    const float *arow = TA + (16 * wave + col) * RS + g;
+    const float *bcol = TB + g * SB + col;
     for (int ch = c0; ch < c0 + nch; ch++) {
 #pragma unroll
-        for (int k = 0; k < 8; k++) TA[sA[k]] = pa[k];
+        for (int k = 0; k < 8; k++) *reinterpret_cast<float2 *>(TA + sA[k]) = pa[k];
 #pragma unroll
         for (int k = 0; k < 4; k++)
-            if (tid + 256 * k < nBt) TB[sB[k]] = pb[k];
+            if (tid + 256 * k < nBt) {
+                *reinterpret_cast<float2 *>(TB + sB[k]) = pb[k];
+                *reinterpret_cast<float2 *>(TB + sB[k] + SB) = make_float2(-pb[k].y, pb[k].x);
+            }
         __syncthreads();
         if (ch + 1 < c0 + nch) load(ch + 1);
 #pragma unroll
         for (int s = 0; s < NT; s++) {
-            const float2 x = arow[2 * s];
-            const float a = cpart ? x.y : x.x;
-            const int y = 2 * s + (g >> 1);
+            const float a = arow[4 * s];
 #pragma unroll
-            for (int cb = 0; cb < NC; cb++) {
-                const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
-                float v = 0.f;
-                if (f < F) {
-                    const float2 bx = TB[y * FP + f];
-                    v = d == cpart ? bx.x : (cpart ? -bx.y : bx.y);
-                }
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, v, acc[cb], 0, 0, 0);
-            }
+            for (int cb = 0; cb < NC; cb++)
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bcol[4 * s * SB + 16 * cb], acc[cb], 0, 0, 0);
         }
         __syncthreads();
     }
     if (ks == 0) {
         // one chunk range: the 64 x F outputs go to C through LDS ([row][f],
-        // row stride F+1, in TA's space), written in C's memory order
-        float *Tf = reinterpret_cast<float *>(TA);
+        // row stride F+2, in TA's space), written in C's memory order
+        const int FP = F + 2;
 #pragma unroll
         for (int cb = 0; cb < NC; cb++) {
             const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
             if (f < F) {
 #pragma unroll
-                for (int v = 0; v < 4; v++) Tf[2 * ((16 * wave + 4 * g + v) * FP + f) + d] = acc[cb][v];
+                for (int v = 0; v < 4; v++) TA[2 * ((16 * wave + 4 * g + v) * FP + f) + d] = acc[cb][v];
             }
         }
         __syncthreads();
+        const float2 *TC = reinterpret_cast<const float2 *>(TA);
         float2 *cb = C + map_apply(maps[SM_RC], r0);
         const int nC = 64 << nf;
         for (int e = tid; e < nC; e += 256)
-            cb[map_apply(maps[SM_EC], e)] = TA[map_apply(maps[SM_ER2], e) * FP + map_apply(maps[SM_EF], e)];
+            cb[map_apply(maps[SM_EC], e)] = TC[map_apply(maps[SM_ER2], e) * FP + map_apply(maps[SM_EF], e)];
         return;
     }
     float *Pf = reinterpret_cast<float *>(P);
@@ -604,7 +610,8 @@ template <int KC, int NC>
 void launch_stream_mx_nc(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
                          hipStream_t s) {
     const int L = op.tile_l;
-    const size_t lds = sizeof(float2) * (((size_t)1 << L) * ((1 << KC) + 1) + ((size_t)1 << L) * ((1 << op.nf) + 1));
+    const int rsa = ((1 << KC) >= 4 ? 2 * (1 << KC) : 8) + 4; // floats per A row, as in the kernel
+    const size_t lds = sizeof(float2) * (((size_t)1 << L) * (rsa / 2) + ((size_t)1 << L) * ((1 << op.nf) + 2));
     const int64_t tiles = (int64_t)1 << (op.nr - L);
     const int64_t res = resident_blocks(reinterpret_cast<const void *>(&k_stream_mx<KC, NC>), lds);
     const dim3 g((unsigned)std::min<int64_t>(tiles, res)), t(256);
