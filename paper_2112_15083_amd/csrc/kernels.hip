@@ -779,9 +779,18 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // Block tile BM x BN complex outputs, BK complex k per stage, 4 waves in a
 // 2 x 2 grid, each wave (BM/2) x (BN/2) as 32 x 32 MFMA blocks.  Operands are
 // staged de-interleaved (separate re / im planes) in LDS, double buffered.
-// C_re += A_re B_re + (-A_im) B_im ; C_im += A_re B_im + A_im B_re.
+// The complex product takes three real products (Gauss):
+//   T1 = A_re B_re, T2 = A_im B_im, T3 = (A_re + A_im)(B_re + B_im),
+//   C_re = T1 - T2, C_im = T3 - T1 - T2,
+// three matrix-core products per complex multiply-add instead of four (the
+// FP32 rounding error grows by about half: T3's terms are up to twice as large).
+// waves per SIMD the registers are held to: the three accumulator sets take
+// 3 * 16 * (BM / 64) * (BN / 64) registers per lane
+constexpr int gemm_waves(int BM, int BN) { return BM * BN > 8192 ? 2 : BM * BN > 4096 ? 3 : 4; }
+
 template <int BM, int BN, int A_KFAST, int B_NFAST>
-__global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves(BM, BN))))
+k_cgemm_f32(GemmArgs g) {
     constexpr int BK = 8;
     constexpr int PAD = 4;
     constexpr int WM = BM / 64, WN = BN / 64; // 32x32 blocks per wave
@@ -849,13 +858,13 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
         }
     };
 
-    floatx16 cre[WM][WN], cim[WM][WN];
+    floatx16 t1[WM][WN], t2[WM][WN], t3[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; i++)
 #pragma unroll
         for (int j = 0; j < WN; j++)
 #pragma unroll
-            for (int v = 0; v < 16; v++) cre[i][j][v] = 0.f, cim[i][j][v] = 0.f;
+            for (int v = 0; v < 16; v++) t1[i][j][v] = 0.f, t2[i][j][v] = 0.f, t3[i][j][v] = 0.f;
 
     const int64_t kb = krange * (K / g.ksplit); // this workgroup's K range
     const int nk = (int)(K / g.ksplit / BK);
@@ -868,28 +877,28 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 2) {
             const int kr = kk + (lane >> 5);
-            float are[WM], aim[WM], anim[WM], bre[WN], bim[WN];
+            float are[WM], aim[WM], asum[WM], bre[WN], bim[WN], bsum[WN];
 #pragma unroll
             for (int i = 0; i < WM; i++) {
                 const int mm = wm * (BM / 2) + i * 32 + (lane & 31);
                 are[i] = As[cur][0][kr][mm];
                 aim[i] = As[cur][1][kr][mm];
-                anim[i] = -aim[i];
+                asum[i] = are[i] + aim[i];
             }
 #pragma unroll
             for (int j = 0; j < WN; j++) {
                 const int nn = wn * (BN / 2) + j * 32 + (lane & 31);
                 bre[j] = Bs[cur][0][kr][nn];
                 bim[j] = Bs[cur][1][kr][nn];
+                bsum[j] = bre[j] + bim[j];
             }
 #pragma unroll
             for (int i = 0; i < WM; i++)
 #pragma unroll
                 for (int j = 0; j < WN; j++) {
-                    cre[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[i], bre[j], cre[i][j], 0, 0, 0);
-                    cre[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(anim[i], bim[j], cre[i][j], 0, 0, 0);
-                    cim[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[i], bim[j], cim[i][j], 0, 0, 0);
-                    cim[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[i], bre[j], cim[i][j], 0, 0, 0);
+                    t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[i], bre[j], t1[i][j], 0, 0, 0);
+                    t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[i], bim[j], t2[i][j], 0, 0, 0);
+                    t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(asum[i], bsum[j], t3[i][j], 0, 0, 0);
                 }
         }
         if (kt + 1 < nk) sstore(cur ^ 1);
@@ -905,7 +914,8 @@ __global__ void __launch_bounds__(256) k_cgemm_f32(GemmArgs g) {
             for (int v = 0; v < 16; v++) {
                 const int64_t m = m0 + wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int64_t n = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
-                C[m * N + n] = make_float2(cre[i][j][v], cim[i][j][v]);
+                const float x1 = t1[i][j][v], x2 = t2[i][j][v];
+                C[m * N + n] = make_float2(x1 - x2, (t3[i][j][v] - x1) - x2);
             }
 }
 
