@@ -53,7 +53,9 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-SHAPES = [(1, 64, 64, 8), (3, 64, 128, 16), (2, 128, 64, 32), (1, 256, 128, 64), (2, 128, 256, 128)]
+# every tile size with 8-deep K stages (K = 8) and with 16-deep ones
+SHAPES = [(1, 64, 64, 8), (3, 64, 128, 16), (2, 128, 64, 32), (1, 256, 128, 64), (2, 128, 256, 128),
+          (2, 128, 64, 8), (1, 128, 128, 8), (2, 64, 128, 8)]
 
 
 @pytest.mark.parametrize("ak", [0, 1])
