@@ -116,14 +116,16 @@ static std::vector<Legs> leaf_leg_sets(const NetSpec &s, const std::vector<char>
     return out;
 }
 
-// Estimated GPU time of one batch under the plan: GEMM flops at 80 % of the
-// FP32 MFMA peak (or 50 % of the algorithmic split-product peak), streaming
-// and permute bytes at half the HBM peak, a few microseconds per launch.
+// Estimated GPU time of one batch under the plan from measured kernel rates:
+// GEMM flops (8 per complex multiply-add) at the rate below, streaming and
+// permute bytes at their measured HBM rates, a few microseconds per launch.
 double estimate_seconds(const PlanCore &p) {
     const Program &pg = p.prog;
-    // measured rates on MI355X: complex64 GEMM ~80% of FP32 MFMA, split GEMM
-    // ~1/3 of its 3-product ceiling, HBM-bound kernels 4.5-5.5 TB/s
-    const double gemm_rate = p.opts.precision == RQC_C64 ? 0.8 * 157.3e12 : 0.33 * 838.9e12;
+    // measured rates on MI355X, 8 flops per complex multiply-add: the complex64
+    // GEMM takes three real products per multiply-add and runs at 129-170
+    // TFLOP/s in this count (75-80 % of the FP32 MFMA peak executed), the split
+    // GEMM at ~1/3 of its 3-product ceiling
+    const double gemm_rate = p.opts.precision == RQC_C64 ? 1.0 * 157.3e12 : 0.33 * 838.9e12;
     // with the global cache a batch runs only the fixed-bit-dependent launches;
     // the rest is filled once and weighed as shared by many batches
     const double w_indep = pg.cache ? 1.0 / 256 : 1.0;
