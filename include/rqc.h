@@ -125,6 +125,12 @@ typedef struct {
        beats the estimate's choice by at least 5 %; the planner's estimate
        alone decides otherwise.  Only for searched trees with full slicing. */
     int32_t autotune;
+    /* 1 = run every streaming step on its own.  By default a streaming step
+       whose result only feeds the next streaming step runs fused with it when
+       their shapes fit the fused kernel: the intermediate stays in LDS instead
+       of going through HBM.  Results agree with the unfused plan to FP32
+       rounding (the second contraction may add its index in another order). */
+    int32_t no_stream_fusion;
 } rqc_plan_opts;
 
 typedef struct {
@@ -155,6 +161,7 @@ typedef struct {
                                   plan when global_cache is set) */
     double est_seconds;        /* the planner's estimate of one batch's GPU time
                                   (what it minimises over candidate trees) */
+    int32_t n_fused;           /* streaming pairs run fused (see no_stream_fusion) */
 } rqc_plan_info_t;
 
 typedef struct {

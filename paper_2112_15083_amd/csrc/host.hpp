@@ -158,9 +158,20 @@ struct SmallTree {
 // B chunks through EB (element -> B offset), BY and BF (element -> y, f).
 // Chunk ranges (2^lk_split of them) write partial sums to a scratch buffer w
 // laid out [split][r][f], summed afterwards in split order.
+// Fused pair (mx2): a streaming step whose large operand is the result of the
+// step before it, C2 = (A1 B1) B2, with the intermediate kept in LDS.  The
+// first step's tile is 64 rows r (six legs of A1: two extra legs, then the
+// second step's four contracted legs, whose batch legs for B1 come last) by
+// all its contracted and new legs; it is the k_stream_mx tile (EA, ER, EY,
+// RA, RB, YB, FB as there, nr / kc / nf of the first step).  The second step
+// takes the tile's 2^(2 + nf) rows r' = (extra legs, first step's new legs)
+// and contracts its index y2 = the four tile bits above the extra legs with B2
+// (YB2, FB2; RB2 gives B2's offset from the outer row bits, which hold all of
+// B2's batch legs).  Its output tile (r', f2) goes to C2 through EC, ER2, EF
+// (element -> C2 offset, r', f2) at RC (outer row bits -> C2 offset).
 enum {
     SM_RA = 0, SM_RB, SM_RC, SM_FB, SM_FC, SM_YA, SM_YB, SM_EA, SM_RE, SM_YE, SM_EC, SM_RE2, SM_FE,
-    SM_ER, SM_EY, SM_ER2, SM_EF, SM_EB, SM_BY, SM_BF, SM_COUNT
+    SM_ER, SM_EY, SM_ER2, SM_EF, SM_EB, SM_BY, SM_BF, SM_RB2, SM_YB2, SM_FB2, SM_COUNT
 };
 struct StreamOp {
     Buf a, b, c;
@@ -170,6 +181,9 @@ struct StreamOp {
     int mx = 0;      // 1: matrix-core tiled kernel
     int lk = 0;      // 1: matrix-core long-contraction kernel
     int lk_split = 0;
+    int mx2 = 0;     // 1: fused pair (then b2 is B2, kc2 / nf2 the second step's)
+    Buf b2;
+    int kc2 = 0, nf2 = 0;
     BitMap m[SM_COUNT];
 };
 

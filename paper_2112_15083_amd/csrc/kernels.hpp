@@ -42,9 +42,9 @@ void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_se
 void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int n_trees, int lds_elems,
                         const float2 *leafbuf, float2 *arena, float2 *cache, hipStream_t s);
 // d_maps: the op's SM_COUNT bit maps in device memory; w: the op's scratch
-// (long form only, else null)
+// (long form only, else null); b2: the second B of a fused pair (else null)
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
-                   float2 *w, hipStream_t s);
+                   float2 *w, const float2 *b2, hipStream_t s);
 // d_desc: the permute descriptor in device memory
 void launch_permute(const PermDesc *d_desc, int64_t n_tiles, const float2 *src, float2 *dst, hipStream_t s);
 // precision: rqc_precision; amax: two device words of scratch (fp16 scaling)

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <functional>
 #include <numeric>
+#include <tuple>
 
 #include "host.hpp"
 
@@ -98,13 +99,18 @@ struct Lowerer {
     // global cache: dep[t] = tensor t depends on the fixed output bits
     std::vector<char> dep;
     bool cache = false;
+    // fused streaming pairs: deferred[t] = step t runs inside its parent's op
+    bool fuse = true;
+    std::vector<char> deferred;
 
-    Lowerer(const Tree &t, const std::vector<Legs> &l, Program &p, const std::vector<char> &leaf_dep, bool cache_)
-        : tree(t), legs(l), prog(p), cache(cache_) {
+    Lowerer(const Tree &t, const std::vector<Legs> &l, Program &p, const std::vector<char> &leaf_dep, bool cache_,
+            bool fuse_)
+        : tree(t), legs(l), prog(p), cache(cache_), fuse(fuse_) {
         nt = t.n_leaves + (int)t.steps.size();
         layout.resize(nt);
         where.resize(nt);
         parent.assign(nt, -1);
+        deferred.assign(nt, 0);
         tensor_alloc.assign(nt, -1);
         dep.assign(nt, 1);
         for (int i = 0; i < t.n_leaves; i++) dep[i] = leaf_dep[i];
@@ -301,6 +307,9 @@ struct Lowerer {
     // and in the result) when that consumer is a streaming step.  Streaming
     // tiles run over non-batch legs, so t keeps these legs at its high
     // positions and leaves its low (contiguous) positions to legs a tile covers.
+    // When that consumer runs fused with its own consumer, the batch legs of
+    // either step cannot be tile rows either (unless the second step
+    // contracts them), so they go high too.
     Legs late_legs(int t) {
         Legs out;
         const int par = parent[t];
@@ -309,6 +318,16 @@ struct Lowerer {
         const Legs &o = legs[a == t ? b : a], &pc = legs[par];
         for (int v : legs[t])
             if (contains(o, v) && contains(pc, v)) out.push_back(v);
+        if (par >= tree.n_leaves && !in_small[par] && fusable(par) && step_legs(par).a == t) {
+            const StepLegs s2 = step_legs(parent[par]);
+            for (int v : legs[t])
+                if (contains(s2.q, v) && !contains(s2.k, v) && !contains(out, v)) out.push_back(v);
+            Legs keep;
+            for (int v : out)
+                if (!contains(s2.k, v)) keep.push_back(v);
+            std::sort(keep.begin(), keep.end());
+            out = keep;
+        }
         return out;
     }
     static std::vector<int> late_last(std::vector<int> v, const Legs &late) {
@@ -363,17 +382,19 @@ struct Lowerer {
         return late_last(LC, late_legs(t));
     }
 
-    void emit_stream(int t) {
-        auto [a, b] = tree.steps[t - tree.n_leaves];
+    // A streaming step's operands (large one first) and result layout: the
+    // large operand's order with its contracted legs replaced in place by the
+    // new legs, then the consumer's preferences (preferred_layout).
+    void stream_layout(int t, int &a, int &b, std::vector<int> &LC, std::vector<int> &con,
+                       std::vector<int> &newb) {
+        std::tie(a, b) = tree.steps[t - tree.n_leaves];
         if (size_of(b) > size_of(a)) std::swap(a, b);
         const Legs &C = legs[t];
         const std::vector<int> &LA = layout[a], &LB = layout[b];
-        std::vector<int> newb;
+        newb.clear(), LC.clear(), con.clear();
         for (int v : LB)
             if (contains(C, v) && pos_in(LA, v) < 0) newb.push_back(v);
-        std::vector<int> LC;
         size_t nb = 0;
-        std::vector<int> con;
         for (int v : LA) {
             if (contains(C, v))
                 LC.push_back(v);
@@ -384,6 +405,217 @@ struct Lowerer {
         }
         for (; nb < newb.size(); nb++) LC.push_back(newb[nb]);
         LC = preferred_layout(t, LC);
+    }
+
+    // Leg classes of a streaming step t (operands a = large, b): contracted k,
+    // new f, batch q (in both operands and the result), rows (A and result).
+    struct StepLegs {
+        int a, b;
+        Legs k, f, q, rows;
+    };
+    StepLegs step_legs(int t) {
+        StepLegs s;
+        std::tie(s.a, s.b) = tree.steps[t - tree.n_leaves];
+        if (size_of(s.b) > size_of(s.a)) std::swap(s.a, s.b);
+        const Legs &A = legs[s.a], &B = legs[s.b], &C = legs[t];
+        for (int v : A) {
+            if (!contains(C, v)) s.k.push_back(v);
+            else {
+                s.rows.push_back(v);
+                if (contains(B, v)) s.q.push_back(v);
+            }
+        }
+        for (int v : B)
+            if (contains(C, v) && !contains(A, v)) s.f.push_back(v);
+        return s;
+    }
+
+    // Can streaming step t1 run fused into its consumer (k_stream_mx2)?  The
+    // consumer streams t1's result with t1 as its large operand; the first
+    // step contracts 2^4 or 2^5 and adds 2^5, the second contracts 2^4 legs
+    // that are rows of the first (at most two of them batch legs of the first)
+    // and adds 2^4; the second step's batch legs are rows of the first outside
+    // the tile; and both steps run in the same cache phase.
+    bool fusable(int t1) {
+        if (!fuse) return false;
+        const int t2 = parent[t1];
+        if (t2 < 0 || in_small[t2] || gemm_worthy(t2)) return false;
+        const StepLegs s1 = step_legs(t1), s2 = step_legs(t2);
+        if (s2.a != t1) return false;
+        if ((s1.k.size() != 4 && s1.k.size() != 5) || s1.f.size() != 5 || s2.k.size() != 4 || s2.f.size() != 4)
+            return false;
+        if (dep[t1] != dep[t2]) return false;
+        int kq = 0;
+        for (int v : s2.k) {
+            if (!contains(s1.rows, v)) return false;
+            kq += contains(s1.q, v);
+        }
+        if (kq > 2) return false;
+        for (int v : s2.q)
+            if (contains(s1.f, v)) return false;
+        int extra = 0;
+        for (int v : s1.rows)
+            extra += !contains(s2.k, v) && !contains(s1.q, v) && !contains(s2.q, v);
+        return extra >= 2 && s1.rows.size() >= 8;
+    }
+
+    // Emit the fused op for the pair (t1 -> t2); false if its tiles do not
+    // allow the kernel's 16-byte accesses (then both steps run separately).
+    bool emit_fused(int t1, int t2) {
+        const StepLegs s1 = step_legs(t1), s2 = step_legs(t2);
+        const std::vector<int> &LA1 = layout[s1.a], &LB1 = layout[s1.b], &LB2 = layout[s2.b];
+        // tile rows: the two lowest legs of A1 that neither step batches over
+        // nor the second contracts, then the second step's contracted legs,
+        // those that index B1 last
+        std::vector<int> ext;
+        for (int v : LA1)
+            if (contains(s1.rows, v) && !contains(s2.k, v) && !contains(s1.q, v) && !contains(s2.q, v))
+                ext.push_back(v);
+        std::vector<int> T(ext.begin(), ext.begin() + 2);
+        for (int v : s2.k)
+            if (!contains(s1.q, v)) T.push_back(v);
+        for (int v : s2.k)
+            if (contains(s1.q, v)) T.push_back(v);
+        // outer rows: batch legs of either step first (a workgroup's tiles then
+        // share B1 and B2), then the rest by A1 position
+        std::vector<int> outer;
+        for (int v : LA1)
+            if (contains(s1.rows, v) && std::find(T.begin(), T.end(), v) == T.end() &&
+                (contains(s1.q, v) || contains(s2.q, v)))
+                outer.push_back(v);
+        for (int v : LA1)
+            if (contains(s1.rows, v) && std::find(T.begin(), T.end(), v) == T.end() &&
+                !(contains(s1.q, v) || contains(s2.q, v)))
+                outer.push_back(v);
+        std::vector<int> rows = T;
+        rows.insert(rows.end(), outer.begin(), outer.end());
+        // C2's layout: the output tile's legs (the two extra legs, the first
+        // step's new legs, the second's) lowest, then the outer rows in A1
+        // order, before the consumer's preferences
+        std::vector<int> LC2(T.begin(), T.begin() + 2);
+        for (int v : LB1)
+            if (contains(s1.f, v)) LC2.push_back(v);
+        for (int v : LB2)
+            if (contains(s2.f, v)) LC2.push_back(v);
+        LC2.insert(LC2.end(), outer.begin(), outer.end());
+        LC2 = preferred_layout(t2, LC2);
+        // index orders: y1 by A1 position, f1 and f2 by C2 position
+        std::vector<int> y1;
+        for (int v : LA1)
+            if (contains(s1.k, v)) y1.push_back(v);
+        std::vector<int> f1(s1.f.begin(), s1.f.end()), f2(s2.f.begin(), s2.f.end());
+        auto by_c2 = [&](int x, int y) { return pos_in(LC2, x) < pos_in(LC2, y); };
+        std::sort(f1.begin(), f1.end(), by_c2);
+        std::sort(f2.begin(), f2.end(), by_c2);
+        auto positions = [&](const std::vector<int> &layout_, const std::vector<int> &ls) {
+            std::vector<int> out(ls.size());
+            for (size_t j = 0; j < ls.size(); j++) out[j] = pos_in(layout_, ls[j]);
+            return out;
+        };
+        StreamOp op;
+        op.mx2 = 1;
+        op.tile_l = 6;
+        op.nr = (int)rows.size();
+        op.kc = (int)s1.k.size();
+        op.nf = 5;
+        op.kc2 = 4;
+        op.nf2 = 4;
+        op.rc = (int)LC2.size();
+        op.m[SM_RA] = make_map(positions(LA1, rows));
+        op.m[SM_RB] = make_map(positions(LB1, rows));
+        op.m[SM_YB] = make_map(positions(LB1, y1));
+        op.m[SM_FB] = make_map(positions(LB1, f1));
+        std::vector<int> rb2 = positions(LB2, rows);
+        for (int i = 0; i < 6; i++) rb2[i] = -1; // B2's contracted legs go through YB2
+        op.m[SM_RB2] = make_map(rb2);
+        op.m[SM_YB2] = make_map(positions(LB2, std::vector<int>(T.begin() + 2, T.end())));
+        op.m[SM_FB2] = make_map(positions(LB2, f2));
+        std::vector<int> rc = positions(LC2, rows);
+        for (int i = 0; i < 6; i++) rc[i] = -1; // the tile's legs: in the C2 tile, or contracted
+        op.m[SM_RC] = make_map(rc);
+        auto idx = [](const std::vector<int> &P, int pos) {
+            return (int)(std::lower_bound(P.begin(), P.end(), pos) - P.begin());
+        };
+        // A1 tile: (six tile rows, contracted legs) by A1 position
+        std::vector<int> PA;
+        for (int i = 0; i < 6; i++) PA.push_back(pos_in(LA1, rows[i]));
+        for (int v : y1) PA.push_back(pos_in(LA1, v));
+        std::sort(PA.begin(), PA.end());
+        std::vector<int> er(PA.size()), ey(PA.size());
+        for (int i = 0; i < 6; i++) er[idx(PA, pos_in(LA1, rows[i]))] = i, ey[idx(PA, pos_in(LA1, rows[i]))] = -1;
+        for (size_t j = 0; j < y1.size(); j++) ey[idx(PA, pos_in(LA1, y1[j]))] = (int)j, er[idx(PA, pos_in(LA1, y1[j]))] = -1;
+        op.m[SM_EA] = make_map(PA);
+        op.m[SM_ER] = make_map(er);
+        op.m[SM_EY] = make_map(ey);
+        // C2 tile: rows r' = (two extra legs, f1), new legs f2, by C2 position
+        std::vector<int> rp = {T[0], T[1]};
+        rp.insert(rp.end(), f1.begin(), f1.end());
+        std::vector<int> PC;
+        for (int v : rp) PC.push_back(pos_in(LC2, v));
+        for (int v : f2) PC.push_back(pos_in(LC2, v));
+        std::sort(PC.begin(), PC.end());
+        std::vector<int> er2(PC.size()), ef(PC.size());
+        for (size_t i = 0; i < rp.size(); i++) er2[idx(PC, pos_in(LC2, rp[i]))] = (int)i, ef[idx(PC, pos_in(LC2, rp[i]))] = -1;
+        for (size_t j = 0; j < f2.size(); j++) ef[idx(PC, pos_in(LC2, f2[j]))] = (int)j, er2[idx(PC, pos_in(LC2, f2[j]))] = -1;
+        op.m[SM_EC] = make_map(PC);
+        op.m[SM_ER2] = make_map(er2);
+        op.m[SM_EF] = make_map(ef);
+        // 16-byte accesses: tile bit 0 is tensor bit 0 on both sides, spans at
+        // 32-bit byte offsets
+        int64_t spanA = 0, spanC = 0;
+        for (int v : PA) spanA += (int64_t)1 << v;
+        for (int v : PC) spanC += (int64_t)1 << v;
+        if (PA[0] != 0 || PC[0] != 0 || spanA >= ((int64_t)1 << 29) || spanC >= ((int64_t)1 << 29)) return false;
+        // commit: the pair's operands, and its result in t2's place
+        layout[t2] = LC2;
+        op.a = buf_of(s1.a);
+        op.b = buf_of(s1.b);
+        op.b2 = buf_of(s2.b);
+        use_tensor(s1.a);
+        use_tensor(s1.b);
+        use_tensor(s2.b);
+        op.c = materialise(t2);
+        const double f = 8.0 * (std::exp2((double)(s1.rows.size() + s1.k.size() + s1.f.size())) +
+                                std::exp2((double)(s2.rows.size() + s2.k.size() + s2.f.size())));
+        const double by_ = 8.0 * (double)(size_of(s1.a) + size_of(s1.b) + size_of(s2.b) + size_of(t2));
+        prog.streams.push_back(op);
+        prog.ops.push_back({OP_STREAM, (int)prog.streams.size() - 1, f, by_, dep[t2]});
+        if (!dep[t2]) prog.flops_indep += f;
+        prog.flops += f;
+        prog.bytes += by_;
+        op_counter++;
+        return true;
+    }
+
+    void emit_stream(int t) {
+        // a step that can run inside its consumer's op waits for it
+        if (!deferred[t] && fusable(t)) {
+            int a, b;
+            std::vector<int> LC, con, newb;
+            stream_layout(t, a, b, LC, con, newb);
+            layout[t] = LC;
+            deferred[t] = 1;
+            return;
+        }
+        {
+            auto [a0, b0] = tree.steps[t - tree.n_leaves];
+            const int big = size_of(b0) > size_of(a0) ? b0 : a0;
+            if (big >= tree.n_leaves && deferred[big] == 1) {
+                if (emit_fused(big, t)) return;
+                deferred[big] = 2; // not fused after all: run it first
+                emit_stream(big);
+            }
+        }
+        auto [a, b] = tree.steps[t - tree.n_leaves];
+        if (size_of(b) > size_of(a)) std::swap(a, b);
+        const Legs &C = legs[t];
+        const std::vector<int> &LA = layout[a], &LB = layout[b];
+        std::vector<int> LC, con, newb;
+        {
+            int a_, b_;
+            stream_layout(t, a_, b_, LC, con, newb);
+        }
+        (void)C;
         layout[t] = LC;
         StreamOp op;
         op.a = buf_of(a);
@@ -830,6 +1062,7 @@ struct Lowerer {
             if (s.c_kind == 2) s.c_off = allocs[s.c_off].off; // cache offsets (kind 3) are final
         for (auto &s : prog.streams) {
             fix(s.a), fix(s.b), fix(s.c);
+            if (s.mx2) fix(s.b2);
             if (s.lk && s.lk_split > 0) fix(s.w);
         }
         for (auto &p : prog.permutes) fix(p.src), fix(p.dst);
@@ -847,9 +1080,9 @@ struct Lowerer {
 // Lower the tree.  leaf_offsets: element offset of each projected leaf in the
 // leaf buffer.  Returns the root layout through `root_layout`.
 Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
-                   const std::vector<char> &leaf_dep, bool cache, std::vector<int> &root_layout) {
+                   const std::vector<char> &leaf_dep, bool cache, bool fuse, std::vector<int> &root_layout) {
     Program prog;
-    Lowerer L(tree, legs, prog, leaf_dep, cache);
+    Lowerer L(tree, legs, prog, leaf_dep, cache, fuse);
     L.run(leaf_offsets);
     root_layout = L.layout[tree.root()];
     return prog;

@@ -9,7 +9,7 @@
 namespace rqc {
 
 Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
-                   const std::vector<char> &leaf_dep, bool cache, std::vector<int> &root_layout);
+                   const std::vector<char> &leaf_dep, bool cache, bool fuse, std::vector<int> &root_layout);
 
 void sort_leaf(Leaf &L) {
     std::vector<int> order(L.legs.size());
@@ -143,8 +143,10 @@ double estimate_seconds(const PlanCore &p) {
             // ~4.5 TB/s, long contractions ~2 TB/s plus their partial-sum pass,
             // the vector fallbacks under 1 TB/s
             const StreamOp &so = pg.streams[op.index];
-            const double rate = so.mx ? 4.5e12 : (so.lk ? 2e12 : 0.8e12);
+            const double rate = so.mx || so.mx2 ? 4.5e12 : (so.lk ? 2e12 : 0.8e12);
             dt = op.bytes / rate + 4e-6;
+            // a fused pair may be bound by its two matrix-core stages instead
+            if (so.mx2) dt = std::max(dt, op.flops / (0.5 * 157.3e12) + 4e-6);
             if (so.lk && so.lk_split > 0) dt += 16.0 * std::exp2((double)(so.lk_split + so.nr + so.nf)) / 2e12 + 4e-6;
         }
         t += (op.kind == OP_SMALL || op.dep) ? dt : w_indep * dt;
@@ -397,7 +399,8 @@ void plan_finish(PlanCore &p) {
     for (int i = 0; i < nleaves; i++)
         for (int v : sp.leaves[i].legs)
             if (is_fixed[v]) leaf_dep[i] = 1;
-    p.prog = lower_tree(p.tree, legs, leaf_off, leaf_dep, p.opts.global_cache != 0, root_layout);
+    p.prog = lower_tree(p.tree, legs, leaf_off, leaf_dep, p.opts.global_cache != 0, p.opts.no_stream_fusion == 0,
+                        root_layout);
     Program &pg = p.prog;
     pg.leafbuf_elems = buf_off;
     if ((size_t)pg.small_lds_elems * 8 > 65536) fail(RQC_EPLAN, "fused subtree needs more than 64 KiB of LDS");
@@ -443,6 +446,8 @@ void plan_finish(PlanCore &p) {
         I.flops_cached = pg.flops_indep * (double)I.n_groups;
     }
     I.est_seconds = estimate_seconds(p);
+    I.n_fused = 0;
+    for (const StreamOp &so : pg.streams) I.n_fused += so.mx2;
 }
 
 } // namespace rqc

@@ -230,9 +230,9 @@ void dump_plan(const rqc_plan &p) {
                 nbat_tile += std::max(0, std::min(hi, L) - lo);
             }
             std::fprintf(stderr, "  stream %s rc=%d kc=%d nr=%d nf=%d tile=%d batch=%d/%d flops=%.3g bytes=%.3g\n",
-                         so.mx ? "mx" : (so.lk ? "lk" : "vec"), so.rc, so.kc, so.nr, so.nf, so.tile_l, nbat_tile, nbat,
-                         op.flops, op.bytes);
-            if (so.mx || so.lk) {
+                         so.mx2 ? "mx2" : so.mx ? "mx" : (so.lk ? "lk" : "vec"), so.rc, so.kc, so.nr, so.nf, so.tile_l,
+                         nbat_tile, nbat, op.flops, op.bytes);
+            if (so.mx || so.lk || so.mx2) {
                 // memory bits of A that a tile covers (bit 0 missing = pairs not contiguous)
                 for (int which : {SM_EA, SM_EC}) {
                     std::fprintf(stderr, "    tile %s bits:", which == SM_EA ? "A" : "C");
@@ -302,7 +302,7 @@ float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hi
             const StreamOp &so = pg.streams[op.index];
             Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
             launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c),
-                          so.lk && so.lk_split > 0 ? ptr(so.w) : nullptr, s);
+                          so.lk && so.lk_split > 0 ? ptr(so.w) : nullptr, so.mx2 ? ptr(so.b2) : nullptr, s);
             break;
         }
         case OP_PERMUTE: {

@@ -37,7 +37,8 @@ class PlanOpts(ctypes.Structure):
                 ("path_trials", ctypes.c_int32),
                 ("path_seed", ctypes.c_uint64), ("profile", ctypes.c_int32), ("dry_run", ctypes.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
-                ("global_cache", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("global_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("no_stream_fusion", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -50,7 +51,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_launches", ctypes.c_int32), ("n_groups", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
                 ("cache_bytes", ctypes.c_int64), ("flops_cached", ctypes.c_double),
-                ("est_seconds", ctypes.c_double)]
+                ("est_seconds", ctypes.c_double), ("n_fused", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

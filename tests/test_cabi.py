@@ -109,6 +109,27 @@ def test_plan_path_round_trip(rqc):
         assert i1[k] == i2[k], k
 
 
+def test_stream_fusion_report(rqc):
+    """On the 30-qubit workload's tree (tests/data/mid_tree.json) the planner
+    fuses the two pairs of consecutive rank-28 streaming steps, cutting their
+    HBM bytes; the opt-out keeps every step separate with the same flops."""
+    import json
+    import os
+    tree = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "mid_tree.json")))
+    cfg = synthetic.CONFIGS["mid"]
+    t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    c = rqc.load_circuit(t)
+    f = rqc.plan_info(rqc.plan_create(c, cfg["open_qubits"], dry_run=1, path=tree["path"], sliced_legs=tree["sliced"]))
+    u = rqc.plan_info(rqc.plan_create(c, cfg["open_qubits"], dry_run=1, path=tree["path"], sliced_legs=tree["sliced"],
+                                      no_stream_fusion=1))
+    assert f["n_fused"] == 2 and u["n_fused"] == 0
+    assert f["flops_per_batch"] == u["flops_per_batch"]
+    assert f["n_launches"] == u["n_launches"] - 2
+    # each fused pair drops one rank-28 intermediate written and read back (2 x 2 GiB)
+    assert u["bytes_per_batch"] - f["bytes_per_batch"] >= 2 * 2 * 8 * 2 ** 28 * 0.99 * f["n_groups"]
+    assert f["est_seconds"] < u["est_seconds"]
+
+
 def test_memory_target_slicing(rqc):
     cfg = synthetic.CONFIGS["mid"]
     t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"])

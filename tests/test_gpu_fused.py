@@ -1,0 +1,68 @@
+"""Fused streaming pairs (k_stream_mx2) on the 30-qubit workload's tree: the
+fused plan against the unfused plan on the same tree and against the oracle's
+stored FP64 amplitudes (tests/golden, written from the oracle only).
+
+Bars: both within the complex64 bar of the FP64 oracle (1e-5).  Fused vs
+unfused within 5e-6, half that bar: the two are FP32 evaluations that differ in
+the order of one step's sums (the fused second contraction may add its four
+contracted legs in another order), so they differ by about the path's own FP32
+error -- 2.7e-6 against FP64 on this workload -- not by one rounding.  Measured:
+1.17e-6."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def rqc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_15083_amd import rqc as lib
+    return lib
+
+
+def test_fused_pairs_match_unfused_and_oracle(rqc):
+    import torch
+    tree = json.load(open(os.path.join(HERE, "data", "mid_tree.json")))
+    cfg = synthetic.CONFIGS["mid"]
+    text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    open_q = cfg["open_qubits"]
+    c = rqc.load_circuit(text)
+    fused = rqc.plan_create(c, open_q, path=tree["path"], sliced_legs=tree["sliced"])
+    plain = rqc.plan_create(c, open_q, path=tree["path"], sliced_legs=tree["sliced"], no_stream_fusion=1)
+    fi, pi = rqc.plan_info(fused), rqc.plan_info(plain)
+    assert fi["n_fused"] == 2 and pi["n_fused"] == 0
+    assert fi["flops_per_batch"] == pi["flops_per_batch"]
+    n = fi["n_qubits"]
+    ref = np.load(os.path.join(HERE, "golden", "mid_seed0_call0.npy"))
+    fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + 0)]
+    outs = []
+    for p in (plain, fused):
+        o = torch.empty((1, 1 << len(open_q), 2), dtype=torch.float32, device="cuda")
+        rqc.contract_amplitudes(p, fb, o)
+        torch.cuda.synchronize()
+        a = o.cpu().numpy()[0]
+        outs.append(a[:, 0].astype(np.float64) + 1j * a[:, 1])
+    assert rel_l2(outs[1], outs[0]) <= 5e-6
+    for a in outs:
+        assert rel_l2(a, ref) <= 1e-5
+    # a second batch with other fixed bits through the same plans
+    fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + 5)]
+    got = []
+    for p in (plain, fused):
+        o = torch.empty((1, 1 << len(open_q), 2), dtype=torch.float32, device="cuda")
+        rqc.contract_amplitudes(p, fb, o)
+        torch.cuda.synchronize()
+        a = o.cpu().numpy()[0]
+        got.append(a[:, 0].astype(np.float64) + 1j * a[:, 1])
+    assert rel_l2(got[1], got[0]) <= 5e-6
