@@ -590,21 +590,22 @@ __global__ void __launch_bounds__(256) k_stream_lk_sum(const float2 *__restrict_
 
 // Fused pair of streaming contractions on matrix cores, C2 = (A1 B1) B2 with
 // the intermediate kept in LDS (the tile legs are described with StreamOp).
-// Stage 1 is the k_stream_mx tile with 64 rows, 2^KC1 contracted and 32 new
-// (one 16-row block per wave, the wave's B1' in registers); its 64 x 32 result
-// goes to LDS as [row][f1] at a row stride of 36 complex.  Stage 2 reads that
-// as 128 rows r' = (row bits 0-1, f1) by 16 contracted y2 = row bits 2-5 --
-// the stride makes a wave's operand reads (16 rows by 4 floats) hit 64
-// distinct banks -- each wave two 16-row blocks against B2' (registers; B2
-// depends only on outer row bits), 16 new legs.  Its 128 x 16 result is staged
-// through the same LDS space ([r'][f2], row stride 18) and stored to C2 with
-// 16-byte stores.  The next tile's A1 is loaded while a tile is computed.
-template <int KC1>
+// Stage 1 is the k_stream_mx tile with 64 rows, 2^KC1 contracted and
+// F1 = 8 NC1 new (16 or 32; one 16-row block per wave, the wave's B1' in
+// registers); its 64 x F1 result goes to LDS as [row][f1] at a row stride of
+// 36 complex.  Stage 2 reads that as 4 F1 rows r' = (row bits 0-1, f1) by 16
+// contracted y2 = row bits 2-5 -- the stride makes a wave's operand reads (16
+// rows by 4 floats) hit 64 distinct banks -- each wave F1 / 16 row blocks of
+// 16 against B2' (registers; B2 depends only on outer row bits), 16 new legs.
+// Its 4 F1 x 16 result is staged through the same LDS space ([r'][f2], row
+// stride 18) and stored to C2 with 16-byte stores.  The next tile's A1 is
+// loaded while a tile is computed.
+template <int KC1, int NC1>
 __global__ void __launch_bounds__(256) k_stream_mx2(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                     const float2 *__restrict__ B2, float2 *__restrict__ C,
                                                     const BitMap *__restrict__ maps, int nr) {
-    constexpr int K1 = 1 << KC1, RSA = 2 * K1 + 4, KP = RSA / 2, NT1 = K1 / 2, NC1 = 4, F1 = 32, FP1 = 36;
-    constexpr int NT2 = 8, NC2 = 2, FP2 = 18;
+    constexpr int K1 = 1 << KC1, RSA = 2 * K1 + 4, KP = RSA / 2, NT1 = K1 / 2, FP1 = 36;
+    constexpr int NT2 = 8, NC2 = 2, FP2 = 18, QB = NC1 / 2; // QB: stage-2 row blocks per wave
     __shared__ float2 TA[64 * KP];
     __shared__ float2 TC[64 * FP1]; // intermediate [64][FP1]; then the output [128][FP2]
     const float *TAf = reinterpret_cast<const float *>(TA);
@@ -612,15 +613,19 @@ __global__ void __launch_bounds__(256) k_stream_mx2(const float2 *__restrict__ A
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15, cpart = g & 1;
     // 16-byte moves of element pairs (tile bit 0 is tensor bit 0): A1's
-    // 2^(6+KC1) elements (the pair index wraps for KC1 = 4) and C2's 2^11
+    // 2^(6+KC1) elements (the pair index wraps for KC1 = 4) and C2's
+    // 2^(9 + log2 NC1), NC1 pairs per thread
     constexpr int hA = (64 << KC1) >> 1;
-    uint32_t oA[4], sA[4], oC[4], sC[4];
+    uint32_t oA[4], sA[4], oC[NC1], sC[NC1];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int ea = 2 * ((tid + 256 * k) & (hA - 1));
         oA[k] = (uint32_t)map_apply(maps[SM_EA], ea) * 8u;
         sA[k] = (uint32_t)(map_apply(maps[SM_ER], ea) * KP + map_apply(maps[SM_EY], ea)) |
                 (uint32_t)(map_apply(maps[SM_ER], ea + 1) * KP + map_apply(maps[SM_EY], ea + 1)) << 16;
+    }
+#pragma unroll
+    for (int k = 0; k < NC1; k++) {
         const int ec = 2 * (tid + 256 * k);
         oC[k] = (uint32_t)map_apply(maps[SM_EC], ec) * 8u;
         sC[k] = (uint32_t)(map_apply(maps[SM_ER2], ec) * FP2 + map_apply(maps[SM_EF], ec)) |
@@ -675,7 +680,7 @@ __global__ void __launch_bounds__(256) k_stream_mx2(const float2 *__restrict__ A
         __syncthreads();
         const int64_t tn = t + G;
         load(tn < n_tiles ? tn : t); // the next tile's A1 (the current one again at the end)
-        // stage 1: this wave's 16 rows by 32 new, into the intermediate
+        // stage 1: this wave's 16 rows by F1 new, into the intermediate
         {
             floatx4 acc[NC1];
 #pragma unroll
@@ -697,14 +702,14 @@ __global__ void __launch_bounds__(256) k_stream_mx2(const float2 *__restrict__ A
             }
         }
         __syncthreads();
-        // stage 2: rows r' = 32 wave + 16 q + col; operand (r', y2 = 2s + g/2,
+        // stage 2: rows r' = 16 (QB wave + q) + col; operand (r', y2 = 2s + g/2,
         // part g%2) is intermediate row (r' & 3) | y2 << 2, column r' >> 2
-        floatx4 acc2[2][NC2];
+        floatx4 acc2[QB][NC2];
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
+        for (int q = 0; q < QB; q++) {
 #pragma unroll
             for (int cb = 0; cb < NC2; cb++) acc2[q][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const int rp = 32 * wave + 16 * q + col;
+            const int rp = 16 * (QB * wave + q) + col;
             const float *arow = TCf + 2 * ((rp & 3) * FP1 + (rp >> 2)) + 8 * FP1 * (g >> 1) + cpart;
 #pragma unroll
             for (int s = 0; s < NT2; s++) {
@@ -716,8 +721,8 @@ __global__ void __launch_bounds__(256) k_stream_mx2(const float2 *__restrict__ A
         }
         __syncthreads(); // every read of the intermediate is done
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const int rb = 32 * wave + 16 * q;
+        for (int q = 0; q < QB; q++) {
+            const int rb = 16 * (QB * wave + q);
 #pragma unroll
             for (int cb = 0; cb < NC2; cb++) {
                 const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
@@ -728,7 +733,7 @@ __global__ void __launch_bounds__(256) k_stream_mx2(const float2 *__restrict__ A
         __syncthreads();
         const __amdgpu_buffer_rsrc_t w = tile_rsrc(C + map_apply(maps[SM_RC], r0));
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < NC1; k++) {
             const float2 lo = TC[sC[k] & 0xffffu], hi = TC[sC[k] >> 16];
             const u32x4 v = {__float_as_uint(lo.x), __float_as_uint(lo.y), __float_as_uint(hi.x), __float_as_uint(hi.y)};
             __builtin_amdgcn_raw_buffer_store_b128(v, w, oC[k], 0, 0);
@@ -779,8 +784,8 @@ void launch_stream_mx(const StreamOp &op, const BitMap *d_maps, const float2 *a,
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
                    float2 *w, const float2 *b2, hipStream_t s) {
     if (op.mx2) {
-        if (op.tile_l != 6 || (op.kc != 4 && op.kc != 5) || op.nf != 5 || op.kc2 != 4 || op.nf2 != 4 || op.nr < 8 ||
-            op.nr > 36 || !b2)
+        if (op.tile_l != 6 || (op.kc != 4 && op.kc != 5) || (op.nf != 4 && op.nf != 5) || op.kc2 != 4 ||
+            op.nf2 != 4 || op.nr < 8 || op.nr > 36 || !b2)
             fail(RQC_EPLAN, "fused streaming pair exceeds the kernel's limits");
         const int64_t tiles = (int64_t)1 << (op.nr - 6);
         auto go = [&](auto kern) {
@@ -788,8 +793,8 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
             hipLaunchKernelGGL(kern, dim3((unsigned)std::min<int64_t>(tiles, res)), dim3(256), 0, s, a, b, b2, c,
                                d_maps, op.nr);
         };
-        if (op.kc == 4) go(k_stream_mx2<4>);
-        else go(k_stream_mx2<5>);
+        if (op.kc == 4) op.nf == 5 ? go(k_stream_mx2<4, 4>) : go(k_stream_mx2<4, 2>);
+        else op.nf == 5 ? go(k_stream_mx2<5, 4>) : go(k_stream_mx2<5, 2>);
         return;
     }
     if (op.mx) {

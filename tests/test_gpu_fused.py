@@ -1,6 +1,7 @@
-"""Fused streaming pairs (k_stream_mx2) on the 30-qubit workload's tree: the
-fused plan against the unfused plan on the same tree and against the oracle's
-stored FP64 amplitudes (tests/golden, written from the oracle only).
+"""Fused streaming pairs (k_stream_mx2) on the 30-qubit workloads' trees
+(tests/data, written by make_trees.py): the fused plan against the unfused plan
+on the same tree and against the oracle's stored FP64 amplitudes (tests/golden,
+written from the oracle only).
 
 Bars: both within the complex64 bar of the FP64 oracle (1e-5).  Fused vs
 unfused within 5e-6, half that bar: the two are FP32 evaluations that differ in
@@ -31,20 +32,23 @@ def rqc():
     return lib
 
 
-def test_fused_pairs_match_unfused_and_oracle(rqc):
+@pytest.mark.parametrize("name,n_fused", [("mid", 2), ("precision", 1)])
+def test_fused_pairs_match_unfused_and_oracle(rqc, name, n_fused):
+    """mid: two pairs whose first step adds 2^5 legs; precision: one pair whose
+    first step adds 2^4."""
     import torch
-    tree = json.load(open(os.path.join(HERE, "data", "mid_tree.json")))
-    cfg = synthetic.CONFIGS["mid"]
+    tree = json.load(open(os.path.join(HERE, "data", f"{name}_tree.json")))
+    cfg = synthetic.CONFIGS[name]
     text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
     open_q = cfg["open_qubits"]
     c = rqc.load_circuit(text)
     fused = rqc.plan_create(c, open_q, path=tree["path"], sliced_legs=tree["sliced"])
     plain = rqc.plan_create(c, open_q, path=tree["path"], sliced_legs=tree["sliced"], no_stream_fusion=1)
     fi, pi = rqc.plan_info(fused), rqc.plan_info(plain)
-    assert fi["n_fused"] == 2 and pi["n_fused"] == 0
+    assert fi["n_fused"] == n_fused and pi["n_fused"] == 0
     assert fi["flops_per_batch"] == pi["flops_per_batch"]
     n = fi["n_qubits"]
-    ref = np.load(os.path.join(HERE, "golden", "mid_seed0_call0.npy"))
+    ref = np.load(os.path.join(HERE, "golden", f"{name}_seed0_call0.npy"))
     fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + 0)]
     outs = []
     for p in (plain, fused):
