@@ -784,8 +784,8 @@ void launch_stream_mx(const StreamOp &op, const BitMap *d_maps, const float2 *a,
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
                    float2 *w, const float2 *b2, hipStream_t s) {
     if (op.mx2) {
-        if (op.tile_l != 6 || (op.kc != 4 && op.kc != 5) || (op.nf != 4 && op.nf != 5) || op.kc2 != 4 ||
-            op.nf2 != 4 || op.nr < 8 || op.nr > 36 || !b2)
+        if (op.tile_l != 6 || (op.kc != 4 && op.kc != 5) || op.nf != 5 || op.kc2 != 4 || op.nf2 != 4 || op.nr < 8 ||
+            op.nr > 36 || !b2)
             fail(RQC_EPLAN, "fused streaming pair exceeds the kernel's limits");
         const int64_t tiles = (int64_t)1 << (op.nr - 6);
         auto go = [&](auto kern) {
@@ -793,8 +793,8 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
             hipLaunchKernelGGL(kern, dim3((unsigned)std::min<int64_t>(tiles, res)), dim3(256), 0, s, a, b, b2, c,
                                d_maps, op.nr);
         };
-        if (op.kc == 4) op.nf == 5 ? go(k_stream_mx2<4, 4>) : go(k_stream_mx2<4, 2>);
-        else op.nf == 5 ? go(k_stream_mx2<5, 4>) : go(k_stream_mx2<5, 2>);
+        if (op.kc == 4) go(k_stream_mx2<4, 4>);
+        else go(k_stream_mx2<5, 4>);
         return;
     }
     if (op.mx) {

@@ -1,5 +1,5 @@
-"""Write the contraction trees of the 30-qubit workloads that the tests run the
-fused streaming pairs on (inputs, not expected values).
+"""Write the contraction tree of the 30-qubit "mid" workload that the tests run
+the fused streaming pairs on (an input, not an expected value).
 
 Each is the tree the library's planner finds with the benchmark's search
 settings (65536 trials, seed 0, the workload's sliced-leg count), stored so
@@ -15,7 +15,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import synthetic  # noqa: E402
 from paper_2112_15083_amd import rqc  # noqa: E402
 
-N_SLICED = {"mid": 6, "precision": 10}
+N_SLICED = {"mid": 6}
 
 
 def main():

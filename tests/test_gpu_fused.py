@@ -1,4 +1,4 @@
-"""Fused streaming pairs (k_stream_mx2) on the 30-qubit workloads' trees
+"""Fused streaming pairs (k_stream_mx2) on the 30-qubit workload's tree
 (tests/data, written by make_trees.py): the fused plan against the unfused plan
 on the same tree and against the oracle's stored FP64 amplitudes (tests/golden,
 written from the oracle only).
@@ -32,10 +32,9 @@ def rqc():
     return lib
 
 
-@pytest.mark.parametrize("name,n_fused", [("mid", 2), ("precision", 1)])
+@pytest.mark.parametrize("name,n_fused", [("mid", 2)])
 def test_fused_pairs_match_unfused_and_oracle(rqc, name, n_fused):
-    """mid: two pairs whose first step adds 2^5 legs; precision: one pair whose
-    first step adds 2^4."""
+    """mid: two pairs, the first steps contracting 2^4 and 2^5."""
     import torch
     tree = json.load(open(os.path.join(HERE, "data", f"{name}_tree.json")))
     cfg = synthetic.CONFIGS[name]
