@@ -98,6 +98,14 @@ def kernel_roofline(prof, precision_is_c64):
         achieved = pc["bytes"] / pc["seconds"] / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                 "frac": achieved / PEAK["hbm_gbs"]}
+        if cls == "stream" and pc["flops"] > 0:
+            # the streaming contractions run their multiply on the FP32 matrix
+            # cores as real block products (8 real flops per complex
+            # multiply-add, as counted); fused pairs and long contractions make
+            # that side a bound too
+            mf = pc["flops"] / pc["seconds"] / 1e12
+            roof["mfma_side"] = {"achieved": mf, "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
+                                 "frac": mf / PEAK["fp32_mfma_tflops"]}
     roof.update({"kernel": cls, "launches": pc["launches"],
                  "avg_launch_us": 1e6 * pc["seconds"] / max(1, pc["launches"]),
                  "bytes_per_launch": pc["bytes"] / max(1, pc["launches"]),
