@@ -462,6 +462,22 @@ struct Lowerer {
         return extra >= 2 && s1.rows.size() >= 8;
     }
 
+    // Legs of t that a fused pair further up contracts, when t reaches that
+    // pair's large operand through one GEMM (whose output keeps the order of
+    // t's free legs): t keeps them first among its low legs, so that the
+    // pair's tile covers the low positions of its large operand.
+    Legs early_legs(int t) {
+        Legs out;
+        const int g = parent[t];
+        if (g < 0 || !gemm_worthy(g)) return out;
+        const int s = parent[g];
+        if (s < 0 || in_small[s] || gemm_worthy(s) || !fusable(s) || step_legs(s).a != g) return out;
+        const StepLegs u1 = step_legs(s), u2 = step_legs(parent[s]);
+        for (int v : legs[t])
+            if (contains(u1.k, v) || contains(u2.k, v)) out.push_back(v);
+        return out;
+    }
+
     // Emit the fused op for the pair (t1 -> t2); false if its tiles do not
     // allow the kernel's 16-byte accesses (then both steps run separately).
     bool emit_fused(int t1, int t2) {
@@ -500,6 +516,10 @@ struct Lowerer {
             if (contains(s1.f, v)) LC2.push_back(v);
         for (int v : LB2)
             if (contains(s2.f, v)) LC2.push_back(v);
+        {   // within the tile's legs, those a fused pair further up contracts first
+            const Legs early = early_legs(t2);
+            std::stable_partition(LC2.begin(), LC2.end(), [&](int v) { return contains(early, v); });
+        }
         LC2.insert(LC2.end(), outer.begin(), outer.end());
         LC2 = preferred_layout(t2, LC2);
         // index orders: y1 by A1 position, f1 and f2 by C2 position
