@@ -113,15 +113,26 @@ def kernel_roofline(prof, precision_is_c64):
     return roof
 
 
+def source_sha256():
+    """One digest over the library sources (kernels and the lowering that
+    decides their tiles and layouts both change the traffic)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2112_15083_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".cpp", ".hpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(cls):
     """HBM traffic per launch from the committed counter summary, if it was taken
-    on the current kernel source (else None)."""
+    on the current library source (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{cls}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2112_15083_amd", "csrc", "kernels.hip"), "rb").read()
-    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("source_sha256") != source_sha256():
         return None
     return rec.get("bytes_per_launch")
 
