@@ -230,6 +230,7 @@ def run_mid_like(args, rqc, torch):
                                f"alpha {alpha}", "qubits": n, "slices": info["n_slices"], "open_batch": 1 << o,
                    "flops_per_step": info["flops_per_batch"], "gemm_flop_share": info["gemm_flop_share"],
                    "max_log2_tensor": info["max_log2_tensor"], "plan_seconds": plan_s,
+                   "launches_per_group": info["n_launches"], "fused_stream_pairs": info["n_fused"],
                    "kernel_seconds": {k: v["seconds"] for k, v in prof.items()}},
         "roofline": kernel_roofline(prof, prec == rqc.C64),
     }
