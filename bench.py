@@ -82,7 +82,7 @@ def cpu_baseline(cfg, text, budget_s=20.0):
 MFMA_FLOPS_PER_CMAC = {True: 6.0, False: 24.0}
 
 
-def kernel_roofline(prof, precision_is_c64):
+def kernel_roofline(prof, precision_is_c64, workload=None):
     """Dominant kernel class by measured time and its achieved fraction."""
     cls = max((k for k in prof if k != "sample"), key=lambda k: prof[k]["seconds"])
     pc = prof[cls]
@@ -109,7 +109,7 @@ def kernel_roofline(prof, precision_is_c64):
     roof.update({"kernel": cls, "launches": pc["launches"],
                  "avg_launch_us": 1e6 * pc["seconds"] / max(1, pc["launches"]),
                  "bytes_per_launch": pc["bytes"] / max(1, pc["launches"]),
-                 "traffic": measured_traffic(cls)})
+                 "traffic": measured_traffic(cls, workload)})
     return roof
 
 
@@ -125,14 +125,21 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(cls):
+def traffic_key(args):
+    """The plan a counter record belongs to: workload, precision, slicing and
+    the tree search that picked it."""
+    return (f"{args.config}:{args.precision}:{'partial' if args.target_fidelity else 'full'}:"
+            f"trials={args.path_trials}:seed={args.path_seed}:autotune={args.autotune}")
+
+
+def measured_traffic(cls, workload):
     """HBM traffic per launch from the committed counter summary, if it was taken
-    on the current library source (else None)."""
+    on this workload and the current library source (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{cls}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != source_sha256():
+    if rec.get("source_sha256") != source_sha256() or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_launch")
 
@@ -232,7 +239,7 @@ def run_mid_like(args, rqc, torch):
                    "max_log2_tensor": info["max_log2_tensor"], "plan_seconds": plan_s,
                    "launches_per_group": info["n_launches"], "fused_stream_pairs": info["n_fused"],
                    "kernel_seconds": {k: v["seconds"] for k, v in prof.items()}},
-        "roofline": kernel_roofline(prof, prec == rqc.C64),
+        "roofline": kernel_roofline(prof, prec == rqc.C64, traffic_key(args)),
     }
     if args.global_cache and not args.target_fidelity:
         # the paper's multi-batch reuse: parts of the contraction that do not
