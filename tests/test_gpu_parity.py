@@ -123,6 +123,37 @@ def test_custom_slice_lists_sum_to_full(rqc):
     assert rel_l2(got[:, 0] + 1j * got[:, 1], ref) <= TOL
 
 
+def test_empty_slice_list_and_no_batches(rqc):
+    """Degenerate calls: an empty slice list is the empty sum (all amplitudes
+    exactly zero, both precisions); no batches writes nothing; a list that
+    splits a batched group is refused before any launch."""
+    import torch
+    text = circuit(4, 4, 8, seed=8)
+    open_q = list(range(8, 16))
+    c = rqc.load_circuit(text)
+    p = rqc.plan_create(c, open_q, n_sliced_target=4, max_log2_batched=1)
+    nb = rqc.plan_info(p)["n_batched"]
+    out = torch.full((2, 256, 2), float("nan"), dtype=torch.float32, device="cuda")
+    out64 = torch.full((2, 256, 2), float("nan"), dtype=torch.float64, device="cuda")
+    rqc.contract_amplitudes(p, [0, 3], out, out64, slice_ids=[])
+    torch.cuda.synchronize()
+    assert torch.equal(out, torch.zeros_like(out))
+    assert torch.equal(out64, torch.zeros_like(out64))
+
+    sentinel = torch.full((1, 256, 2), 7.0, dtype=torch.float32, device="cuda")
+    rqc.contract_amplitudes(p, [], sentinel)
+    torch.cuda.synchronize()
+    assert bool((sentinel == 7.0).all())
+
+    if nb > 0:
+        with pytest.raises(rqc.RqcError, match="whole batched groups"):
+            rqc.contract_amplitudes(p, [0], sentinel, slice_ids=[0])
+    with pytest.raises(rqc.RqcError, match="beyond the sliced legs"):
+        rqc.contract_amplitudes(p, [0], sentinel, slice_ids=[1 << 4])
+    torch.cuda.synchronize()
+    assert bool((sentinel == 7.0).all())
+
+
 def test_sampler_batches_mode_bit_exact(rqc):
     import torch
     text = circuit(4, 4, 10, seed=9)
