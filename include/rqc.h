@@ -256,7 +256,10 @@ void rqc_plan_destroy(rqc_plan *p);
  * plan's fixed slice order (independent of how slices are grouped).
  *   slice_ids: host array of slice ids, or NULL for the plan's default list
  *     (all 2^|I| slices, or X x {0,1}^{|I|-|S|} under partial slicing).  A
- *     custom list must be a union of whole batched-slice groups.
+ *     custom list must be a union of whole batched-slice groups with no id
+ *     repeated and no bit above the sliced legs (else RQC_EINVAL before any
+ *     launch); an empty list (n_slices = 0, non-NULL) is the empty sum and
+ *     writes exact zeros.  n_batches = 0 writes nothing.
  *   out_amps: device complex64 [n_batches][2^n_open].
  *   out_f64: optional device complex128 [n_batches][2^n_open] receiving the
  *     same normalised amplitudes before rounding to complex64.
