@@ -125,11 +125,17 @@ def source_sha256():
     return h.hexdigest()
 
 
-def traffic_key(args):
+def tree_digest(rqc, plan):
+    """Short digest of a plan's contraction tree and sliced legs: the autotune
+    may keep a different tree on another run."""
+    tree = json.dumps([rqc.plan_path(plan), rqc.plan_sliced_legs(plan)])
+    return hashlib.sha256(tree.encode()).hexdigest()[:16]
+
+
+def traffic_key(args, tree):
     """The plan a counter record belongs to: workload, precision, slicing and
-    the tree search that picked it."""
-    return (f"{args.config}:{args.precision}:{'partial' if args.target_fidelity else 'full'}:"
-            f"trials={args.path_trials}:seed={args.path_seed}:autotune={args.autotune}")
+    the contraction tree."""
+    return f"{args.config}:{args.precision}:{'partial' if args.target_fidelity else 'full'}:tree={tree}"
 
 
 def measured_traffic(cls, workload):
@@ -223,6 +229,7 @@ def run_mid_like(args, rqc, torch):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     prof = rqc.plan_profile(plan)
+    tree = tree_digest(rqc, plan)
     amps_s = args.steps * (1 << o) / elapsed
     line = {
         "metric": METRIC, "value": amps_s, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
@@ -238,8 +245,8 @@ def run_mid_like(args, rqc, torch):
                    "flops_per_step": info["flops_per_batch"], "gemm_flop_share": info["gemm_flop_share"],
                    "max_log2_tensor": info["max_log2_tensor"], "plan_seconds": plan_s,
                    "launches_per_group": info["n_launches"], "fused_stream_pairs": info["n_fused"],
-                   "kernel_seconds": {k: v["seconds"] for k, v in prof.items()}},
-        "roofline": kernel_roofline(prof, prec == rqc.C64, traffic_key(args)),
+                   "tree_sha256": tree, "kernel_seconds": {k: v["seconds"] for k, v in prof.items()}},
+        "roofline": kernel_roofline(prof, prec == rqc.C64, traffic_key(args, tree)),
     }
     if args.global_cache and not args.target_fidelity:
         # the paper's multi-batch reuse: parts of the contraction that do not
