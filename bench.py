@@ -1,27 +1,28 @@
 """Throughput of the sliced-contraction sampler on one MI355X.
 
-One step = one open batch of amplitudes through the whole hot path: leaf
-selection per slice group, the contraction program (fused small subtrees,
-streaming contractions, permutes, MFMA complex GEMMs), the FP64 cross-slice
-sum, normalisation, and rejection sampling over the batch's sub-batches of 64.
-Fixed output bits are fresh per step (seeded).  Prints one JSON line; its
-"global_cache" object times the same steps again on a plan that keeps the
-fixed-bit-independent parts of the contraction per slice group (the headline
-value recomputes everything every step).
+Default workload ("large", the 53-qubit share): a 6x9 grid minus site (0,4),
+20 cycles, 2^12 open batch, contraction intermediates bounded by 2^30
+elements.  Partial slicing (Sec. I.B-I.C, Appendix B) at target fidelity
+2^-18 (the kept fraction 2^10 / 2^28 of the workload): 21 partially sliced
+vertices near the inputs, their norms R[i] (2^21 entries) contracted on the
+GPU from the doubled network, X and F by Alg. 1.  The job is the slice list
+X x {0,1}^(|I|-|S|); one GPU's share is 2^10 of its slices (the top-R index
+with its first 2^10 completions).  One step = one fixed group of the share's
+slices for one fresh batch of fixed bits (contraction, FP64 slice sum,
+normalisation by 1/sqrt(F), rejection sampling of the 64 sub-batches); the
+share's rate is derived from the steps (the groups have identical shapes) and
+labelled as such.
 
-Workloads:
-  mid (default)  5x6 grid, 14 cycles, 6 sliced legs (64 slices), 2^12 batch
-  precision      5x6 grid, 16 cycles, 10 sliced legs (1024 slices), 2^14 batch,
-                 in complex64 / bf16x3 / fp16x3 (--precision)
-  large          53 qubits (6x9 minus (0,4)), 20 cycles: one GPU's share (2^10
-                 slices) of a contraction sliced to 2^30-element intermediates,
-                 timed on a prefix of the slice list and extrapolated (labelled)
-  --serve        the serving loop on a Poisson stream of synthetic requests
+Other workloads (--config):
+  mid        5x6 grid, 14 cycles, 6 sliced legs (64 slices), 2^12 batch; one
+             step = one batch through the whole path, plus a global-cache run
+  precision  5x6 grid, 16 cycles, 10 sliced legs (1024 slices), 2^14 batch,
+             in complex64 / bf16x3 / fp16x3 (--precision)
+  tiny       3x4 grid, 8 cycles, all 12 qubits open
+  --serve    the serving loop on a Poisson stream of synthetic requests
   --copy-calibration  a plain 1 GiB device copy, for scaling HBM counters
 
-Plans come from a 65536-trial tree search whose 4 best estimated trees are
-timed on the GPU (--path-trials, --autotune); planning is reported separately
-(plan_seconds) and is not part of a step.
+Planning is reported separately (plan_seconds) and is not part of a step.
 """
 from __future__ import annotations
 
@@ -80,37 +81,114 @@ def cpu_baseline(cfg, text, budget_s=20.0):
 # real products (Gauss), the split GEMMs three bf16/fp16 products of the 2K-long
 # interleaved real view for each of the real and imaginary outputs
 MFMA_FLOPS_PER_CMAC = {True: 6.0, False: 24.0}
+EXEC_PEAK_TFLOPS = {0: PEAK["fp32_mfma_tflops"], 1: PEAK["bf16_mfma_tflops"]}
 
 
-def kernel_roofline(prof, precision_is_c64, workload=None):
-    """Dominant kernel class by measured time and its achieved fraction."""
-    cls = max((k for k in prof if k != "sample"), key=lambda k: prof[k]["seconds"])
-    pc = prof[cls]
-    if cls == "gemm":
-        peak = PEAK["fp32_mfma_tflops"] if precision_is_c64 else PEAK["bf16_mfma_tflops"]
-        # pc["flops"] counts 8 per complex multiply-add; the matrix cores execute
-        # MFMA_FLOPS_PER_CMAC of them
-        achieved = pc["flops"] * MFMA_FLOPS_PER_CMAC[precision_is_c64] / 8.0 / pc["seconds"] / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "flops_per_complex_mac": MFMA_FLOPS_PER_CMAC[precision_is_c64],
-                "complex_tflops_8_per_mac": pc["flops"] / pc["seconds"] / 1e12}
+def op_tmin(rec):
+    """Binding-roof time of an op's launches: the larger of its executed
+    matrix-core (or vector) flops at that unit's peak and its algorithmic
+    bytes at the HBM peak."""
+    t_flop = rec["exec_flops"] / (EXEC_PEAK_TFLOPS[rec["exec_kind"]] * 1e12)
+    t_byte = rec["bytes"] / (PEAK["hbm_gbs"] * 1e9)
+    return max(t_flop, t_byte), t_flop, t_byte
+
+
+def kernel_roofline(op_recs, workload=None):
+    """The dominant kernel class by measured time and its place under its
+    binding roof.  Per op the binding roof is whichever of the matrix cores
+    (executed flops) and HBM (algorithmic bytes) takes longer; `frac` is the
+    class's achieved rate over the peak of the roof that binds most of its
+    minimum time, and `binding_frac` = sum of per-op minimum times / measured."""
+    classes = {}
+    for r in op_recs:
+        if r["cls"] == "sample":
+            continue
+        c = classes.setdefault(r["cls"], dict(seconds=0.0, flops=0.0, bytes=0.0, exec_flops=0.0, launches=0,
+                                              tmin=0.0, t_flop=0.0, t_byte=0.0, kinds=set()))
+        tm, tf, tb = op_tmin(r)
+        c["seconds"] += r["seconds"]
+        c["flops"] += r["flops"]
+        c["bytes"] += r["bytes"]
+        c["exec_flops"] += r["exec_flops"]
+        c["launches"] += r["launches"]
+        c["tmin"] += tm
+        c["t_flop"] += tf if tf >= tb else 0.0
+        c["t_byte"] += tb if tb > tf else 0.0
+        if r["exec_flops"] > 0:
+            c["kinds"].add(r["exec_kind"])
+    cls = max(classes, key=lambda k: classes[k]["seconds"])
+    c = classes[cls]
+    sec = c["seconds"]
+    kind = max(c["kinds"]) if c["kinds"] else 0
+    mf = c["exec_flops"] / sec / 1e12
+    bw = c["bytes"] / sec / 1e9
+    mfma = {"achieved": mf, "peak": EXEC_PEAK_TFLOPS[kind], "unit": "TFLOP/s", "frac": mf / EXEC_PEAK_TFLOPS[kind]}
+    hbm = {"achieved": bw, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": bw / PEAK["hbm_gbs"]}
+    if c["t_flop"] >= c["t_byte"]:
+        roof, other = dict(bound="mfma", **mfma), ("hbm_side", hbm)
     else:
-        achieved = pc["bytes"] / pc["seconds"] / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                "frac": achieved / PEAK["hbm_gbs"]}
-        if cls == "stream" and pc["flops"] > 0:
-            # the streaming contractions run their multiply on the FP32 matrix
-            # cores as real block products (8 real flops per complex
-            # multiply-add, as counted); fused pairs and long contractions make
-            # that side a bound too
-            mf = pc["flops"] / pc["seconds"] / 1e12
-            roof["mfma_side"] = {"achieved": mf, "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
-                                 "frac": mf / PEAK["fp32_mfma_tflops"]}
-    roof.update({"kernel": cls, "launches": pc["launches"],
-                 "avg_launch_us": 1e6 * pc["seconds"] / max(1, pc["launches"]),
-                 "bytes_per_launch": pc["bytes"] / max(1, pc["launches"]),
+        roof, other = dict(bound="hbm", **hbm), ("mfma_side", mfma)
+    roof[other[0]] = other[1]
+    roof.update({"binding_frac": c["tmin"] / sec, "kernel": cls, "launches": c["launches"],
+                 "avg_launch_us": 1e6 * sec / max(1, c["launches"]),
+                 "bytes_per_launch": c["bytes"] / max(1, c["launches"]),
+                 "exec_flops_per_launch": c["exec_flops"] / max(1, c["launches"]),
+                 "complex_tflops_8_per_mac": c["flops"] / sec / 1e12,
                  "traffic": measured_traffic(cls, workload)})
     return roof
+
+
+def path_roofline(op_recs, measured_seconds, precision_is_c64=True):
+    """Sum over the contraction launches of max(algorithmic flops / matrix-core
+    peak, algorithmic bytes / HBM peak), divided by the measured time of the
+    same steps.  Algorithmic flops count 8 per complex multiply-add, against the
+    FP32 peak (complex64) or the 3-product ceiling of the split GEMMs
+    (2516.6 x 8/24 TFLOP/s); permutes, leaf selection, accumulation and the
+    sampler have no minimum time of their own and count against the fraction."""
+    t = 0.0
+    for r in op_recs:
+        if r["cls"] not in ("gemm", "stream", "small_trees"):
+            continue
+        peak = PEAK["fp32_mfma_tflops"]
+        if r["cls"] == "gemm" and r["exec_kind"] == 1:
+            peak = PEAK["bf16_mfma_tflops"] * 8.0 / 24.0
+        t += max(r["flops"] / (peak * 1e12), r["bytes"] / (PEAK["hbm_gbs"] * 1e9))
+    return {"tmin_seconds": t, "measured_seconds": measured_seconds, "frac": t / measured_seconds}
+
+
+def class_seconds(op_recs):
+    out = {}
+    for r in op_recs:
+        out[r["cls"]] = out.get(r["cls"], 0.0) + r["seconds"]
+    return out
+
+
+class SamplerTimer:
+    """HIP events around the sampler calls on the stream they run on (the
+    sampler entry point synchronises that stream before returning, so the
+    second event also covers the host's return from the call)."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+        self.pairs = []
+
+    def __enter__(self):
+        self.a = self.torch.cuda.Event(enable_timing=True)
+        self.a.record(self.stream)
+
+    def __exit__(self, *exc):
+        b = self.torch.cuda.Event(enable_timing=True)
+        b.record(self.stream)
+        self.pairs.append((self.a, b))
+
+    def reset(self):
+        self.pairs = []
+
+    def record(self):
+        self.torch.cuda.synchronize()
+        sec = sum(a.elapsed_time(b) for a, b in self.pairs) * 1e-3
+        return {"cls": "sample", "op": -1, "launches": len(self.pairs), "seconds": sec, "flops": 0.0,
+                "bytes": 0.0, "exec_flops": 0.0, "exec_kind": 0}
 
 
 def source_sha256():
@@ -174,12 +252,15 @@ def run_mid_like(args, rqc, torch):
     samples = torch.zeros(1 << (o - 6), dtype=torch.int64, device="cuda")
     alpha = cfg["alpha"]
 
+    sampler_time = SamplerTimer(torch, stream)
+
     def step(i, record=None, pl=None):
         fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + i)]
         rqc.contract_amplitudes(pl or plan, fb, out, out64, stream=stream)
-        n_out, st, _ = rqc.rejection_sample(out, fb, open_q, n, samples.numel(), samples, alpha=alpha,
-                                            F_norm=1.0, seed=synthetic.SAMPLER_SEED,
-                                            batch_index_base=i << (o - 6), stream=stream)
+        with sampler_time:
+            n_out, st, _ = rqc.rejection_sample(out, fb, open_q, n, samples.numel(), samples, alpha=alpha,
+                                                F_norm=1.0, seed=synthetic.SAMPLER_SEED,
+                                                batch_index_base=i << (o - 6), stream=stream)
         if record is not None:
             record.append(n_out)
         return n_out
@@ -218,6 +299,7 @@ def run_mid_like(args, rqc, torch):
         step(1 + w)
     torch.cuda.synchronize()
     rqc.plan_profile_reset(plan)
+    sampler_time.reset()
     lat = []
     accepted = []
     torch.cuda.synchronize()
@@ -228,7 +310,7 @@ def run_mid_like(args, rqc, torch):
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    prof = rqc.plan_profile(plan)
+    op_recs = rqc.plan_profile_ops(plan) + [sampler_time.record()]
     tree = tree_digest(rqc, plan)
     amps_s = args.steps * (1 << o) / elapsed
     line = {
@@ -245,8 +327,9 @@ def run_mid_like(args, rqc, torch):
                    "flops_per_step": info["flops_per_batch"], "gemm_flop_share": info["gemm_flop_share"],
                    "max_log2_tensor": info["max_log2_tensor"], "plan_seconds": plan_s,
                    "launches_per_group": info["n_launches"], "fused_stream_pairs": info["n_fused"],
-                   "tree_sha256": tree, "kernel_seconds": {k: v["seconds"] for k, v in prof.items()}},
-        "roofline": kernel_roofline(prof, prec == rqc.C64, traffic_key(args, tree)),
+                   "tree_sha256": tree, "kernel_seconds": class_seconds(op_recs)},
+        "roofline": kernel_roofline(op_recs, traffic_key(args, tree)),
+        "path_roofline": path_roofline(op_recs, elapsed),
     }
     if args.global_cache and not args.target_fidelity:
         # the paper's multi-batch reuse: parts of the contraction that do not
@@ -287,51 +370,223 @@ def run_mid_like(args, rqc, torch):
     return line
 
 
+LARGE_F = 2.0 ** -18     # target fidelity: the kept fraction 2^10 / 2^28
+LARGE_SHARE = 1 << 10    # slices in one GPU's share
+LARGE_TRIALS = 4096      # tree-search trials per seed
+LARGE_SEEDS = 4          # seeds searched; the best estimated job time is kept
+
+
+def plan_large(rqc, circ, open_q, args):
+    """Tree and sliced legs for the 53-qubit partial plan: a host-only search per
+    seed; the plan with the smallest estimated total time of the whole job (all
+    2^|I| slices) wins.  Returns (path, legs, record)."""
+    best = None
+    tried = []
+    for seed in range(args.large_seeds):
+        p = rqc.plan_create(circ, open_q, max_log2_tensor=30, n_sliced_target=-1, max_log2_batched=30,
+                            path_trials=args.path_trials, path_seed=seed, target_fidelity=LARGE_F, dry_run=1)
+        path, legs = rqc.plan_path(p), rqc.plan_sliced_legs(p)
+        # the same tree and legs with every leg summed: its estimate covers all slices
+        q = rqc.plan_create(circ, open_q, path=path, sliced_legs=legs, max_log2_batched=30, dry_run=1)
+        qi = rqc.plan_info(q)
+        tried.append({"seed": seed, "n_sliced": len(legs), "est_seconds_all_slices": qi["est_seconds"],
+                      "flops_per_slice": qi["flops_per_batch"] / qi["n_slices"]})
+        if best is None or qi["est_seconds"] < best[2]["est_seconds_all_slices"]:
+            best = (path, legs, tried[-1])
+    return best[0], best[1], tried
+
+
+def share_ids(legs, S, x, count, batched):
+    """Slice ids of index x of the partially sliced legs S (bit t of x = S[t])
+    with the first `count` completions of the other sliced legs.  Completions
+    enumerate the batched legs first (so every run of 2^|batched| ids is one
+    whole batched group), then the looped legs in ascending slice-id bit."""
+    pos = {v: t for t, v in enumerate(legs)}
+    base = 0
+    for t, v in enumerate(S):
+        if (x >> t) & 1:
+            base |= 1 << pos[v]
+    bset = set(batched)
+    rest = sorted(pos[v] for v in batched) + sorted(pos[v] for v in legs if v not in set(S) and v not in bset)
+    ids = []
+    for c in range(count):
+        sid = base
+        for j, b in enumerate(rest):
+            if (c >> j) & 1:
+                sid |= 1 << b
+        ids.append(sid)
+    return ids
+
+
 def run_large(args, rqc, torch):
-    """One GPU's share of the 53-qubit contraction: slices chosen so that no
-    intermediate exceeds 2^30 elements, a share of 2^10 of them; a prefix of
-    the slice list is timed and the share, and the 3125 calls that 1e5 samples
-    need, are extrapolated linearly (labelled as such)."""
+    """One GPU's share of the 53-qubit partial contraction (see the module
+    docstring).  Steps time fixed groups of the share's slices; the share's
+    rate is derived from them."""
+    from paper_2112_15083_amd import estimates
     torch.cuda.set_device(0)
     cfg = synthetic.CONFIGS["large"]
     text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
     n = cfg["rows"] * cfg["cols"] - len(cfg["removed"])
     open_q = list(cfg["open_qubits"])
     o = len(open_q)
+    alpha = cfg["alpha"]
     circ = rqc.load_circuit(text)
     t0 = time.perf_counter()
-    # full slicing to a 2^30-element memory bound; the share is the first 2^10
-    # slices of the slice list.  Partial slicing is not used here: on this
-    # path its norm network (the doubled circuit) costs far more than the share
-    plan = rqc.plan_create(circ, open_q, max_log2_tensor=30, n_sliced_target=-1, max_log2_batched=30,
-                           path_trials=args.path_trials, profile=1)
-    plan_s = time.perf_counter() - t0
+    path, legs, tried = plan_large(rqc, circ, open_q, args)
+    search_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = rqc.plan_create(circ, open_q, path=path, sliced_legs=legs, max_log2_tensor=30, max_log2_batched=30,
+                           target_fidelity=LARGE_F, profile=1)
+    torch.cuda.synchronize()
+    norms_s = time.perf_counter() - t0
     info = rqc.plan_info(plan)
-    ids = rqc.plan_slices(plan, cap=args.large_prefix)
+    S, X, R = rqc.plan_partial(plan)
+    R = np.asarray(R)
+    k = len(S)
+    # the plan's batched legs: legs carried as a tensor mode (slice ids must keep their groups whole)
+    group = 1 << info["n_batched"]
+    batched = []
+    if info["n_batched"]:
+        full = rqc.plan_slices(plan, cap=group)
+        bits = 0
+        for sid in full:
+            bits |= sid ^ full[0]
+        batched = [v for t, v in enumerate(legs) if (bits >> t) & 1]
+    ids = share_ids(legs, S, X[0], LARGE_SHARE, batched)
+    G = args.large_group
+    assert LARGE_SHARE % G == 0 and G % group == 0
+    n_groups = LARGE_SHARE // G
     out = torch.empty((1, 1 << o, 2), dtype=torch.float32, device="cuda")
-    fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED)]
+    samples = torch.zeros(1 << (o - 6), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    sampler_time = SamplerTimer(torch, stream)
+    p_j_seen = []
+
+    def step(i, record=None):
+        fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + i)]
+        g = i % n_groups
+        rqc.contract_amplitudes(plan, fb, out, slice_ids=ids[g * G:(g + 1) * G], stream=stream)
+        with sampler_time:
+            n_out, st, _ = rqc.rejection_sample(out, fb, open_q, n, samples.numel(), samples, alpha=alpha,
+                                                F_norm=1.0, seed=synthetic.SAMPLER_SEED,
+                                                batch_index_base=i << (o - 6), stream=stream)
+        if record is not None:
+            record.append((n_out, st))
+
+    for w in range(args.warmup):
+        step(w)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rqc.contract_amplitudes(plan, fb, out, slice_ids=ids)
+    rqc.plan_profile_reset(plan)
+    sampler_time.reset()
+    lat, rec = [], []
+    t_start = time.perf_counter()
+    for s_ in range(args.steps):
+        ts = time.perf_counter()
+        step(args.warmup + s_, rec)  # the sampler synchronises the stream
+        lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
-    prof = rqc.plan_profile(plan)
-    share = 1 << 10
-    per_slice = dt / len(ids)
-    t_share = per_slice * share
-    calls = int(np.ceil(2 * 1e5 / (1 << (o - 6))))
-    flops_per_slice = info["flops_per_batch"] / info["n_slices"]
-    return {"metric": METRIC, "workload": "large: 6x9 grid minus (0,4), 53 qubits, 20 cycles, one GPU's share "
-                                          "of 2^10 slices of a 2^30-element-bounded sliced contraction",
-            "plan_seconds": plan_s, "n_sliced": info["n_sliced"], "total_slices": info["n_slices"],
-            "flops_per_slice": flops_per_slice, "max_log2_tensor": info["max_log2_tensor"],
-            "prefix_slices": len(ids), "prefix_seconds": dt,
-            "tflops": flops_per_slice * len(ids) / dt / 1e12,
-            "extrapolated_seconds_per_share": t_share,
-            "extrapolated_seconds_1e5_samples_at_share": t_share * calls, "calls_for_1e5_samples": calls,
-            "label": "measured on a prefix of the slice list, extrapolated linearly (labelled)",
-            "kernel_seconds": {k: v["seconds"] for k, v in prof.items()},
-            "roofline": kernel_roofline(prof, True)}
+    elapsed = time.perf_counter() - t_start
+    op_recs = rqc.plan_profile_ops(plan) + [sampler_time.record()]
+    flops_per_slice = info["flops_per_batch"] / info["n_slices"] if info["n_slices"] else 0.0
+    step_s = elapsed / args.steps
+    share_s = step_s * n_groups
+    job_slices = info["n_slices"]
+    n_shares = job_slices // LARGE_SHARE
+    # fidelity estimate of the job (Sec. II.B-C): F from the norms; eps from the
+    # Porter-Thomas expectation at this alpha (the measured eps_J of a group's
+    # partial sums is not the job's: its amplitudes are a fraction of psi_X)
+    eps_pt = estimates.expected_eps(1 << 6, alpha)
+    F = info["fidelity"]
+    bound = estimates.fidelity_bound(F, eps_pt)
+    calls_1e5 = int(np.ceil(alpha * 1e5 / (1 << (o - 6))))
+    line = {
+        "metric": METRIC, "value": (1 << o) / share_s, "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * step_s, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE["c64"], "data": "synthetic",
+        "value_note": f"2^{o} amplitudes of one share ({LARGE_SHARE} slices) per share time; a step is "
+                      f"{G} slices of the share ({n_groups} steps per share, identical shapes): share time = "
+                      f"ms_per_step x {n_groups}, derived, not timed as one call",
+        "tflops": G * flops_per_slice / step_s / 1e12,
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "rel_l2_vs_fp64": None,
+        "partial": {
+            "target_fidelity": LARGE_F, "k": k, "n_sliced": len(legs), "X": len(X), "F": F,
+            "F_lower_bound_eq2": len(X) / 2.0 ** k, "sum_R": float(R.sum()),
+            "R_table1": {"sd_normalised": float(np.sqrt((2.0 ** k) * np.var(R * 2.0 ** k) / 2.0 ** k)),
+                         "range_normalised": [float(R.min() * 2.0 ** k), float(R.max() * 2.0 ** k)]},
+            "norm_network_seconds": norms_s, "job_slices": job_slices, "shares_per_job": n_shares,
+            "share": f"index X[0] (top R) with its first {LARGE_SHARE} completions",
+            "eps_expected_porter_thomas": eps_pt, "fidelity_bound_eq9": bound,
+            "samples_note": "a share's amplitudes are a partial sum of psi_X / sqrt(F); samples of the job need "
+                            "all its shares, so the sampler is timed here on the share groups' partial sums "
+                            f"(accepted: {sum(r[0] for r in rec)} over {args.steps} steps)",
+            "one_gpu_seconds_1e5_samples_extrapolated": share_s * n_shares * calls_1e5,
+            "calls_for_1e5_samples": calls_1e5},
+        "config": {"workload": f"large: 6x9 grid minus (0,4), 53 qubits, 20 cycles, 2^{o} open batch, "
+                               f"intermediates <= 2^30 elements; partial slicing at f = 2^-18: |I| = {len(legs)} "
+                               f"sliced legs, k = {k} near-input partial legs, R on 2^{k} entries, "
+                               f"|X| = {len(X)}; one GPU's share = {LARGE_SHARE} of the job's {job_slices} slices; "
+                               f"step = {G} slices of the share + sampling of the batch's 64 sub-batches",
+                   "qubits": n, "open_batch": 1 << o, "slices_per_step": G, "share_slices": LARGE_SHARE,
+                   "flops_per_slice": flops_per_slice, "flops_per_share": flops_per_slice * LARGE_SHARE,
+                   "gemm_flop_share": info["gemm_flop_share"], "max_log2_tensor": info["max_log2_tensor"],
+                   "plan_seconds": {"tree_search": search_s, "plan_and_norms": norms_s},
+                   "search": tried, "launches_per_group": info["n_launches"],
+                   "tree_sha256": tree_digest(rqc, plan), "kernel_seconds": class_seconds(op_recs),
+                   "share_seconds_derived": share_s},
+        "roofline": kernel_roofline(op_recs, None),
+        "path_roofline": path_roofline(op_recs, elapsed),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_large(text, share_s, o)
+    return line
+
+
+def cpu_baseline_large(text, share_s, o, budget_s=20.0):
+    """The oracle's FP64 state vector on all host cores cannot hold 53 qubits:
+    it is timed per gate at 28 qubits over a prefix of this circuit's gate
+    list restricted to the first 28 qubits, and extrapolated by 2^25 in state
+    size to the 53-qubit circuit (labelled)."""
+    from oracle import sv as osv
+    lines = text.splitlines()
+    keep = []
+    n_small = 28
+    for ln in lines:
+        tok = ln.split()
+        if tok and tok[0] == "qubits":
+            keep.append(f"qubits {n_small}")
+        elif tok and tok[0] in ("sx", "sy", "sw"):
+            if int(tok[2]) < n_small:
+                keep.append(ln)
+        elif tok and tok[0] == "fsim":
+            if int(tok[2]) < n_small and int(tok[3]) < n_small:
+                keep.append(ln)
+        elif tok and tok[0] in ("grid", "removed"):
+            continue
+        else:
+            keep.append(ln)
+    small = "\n".join(keep) + "\n"
+    n_gates_small = osv.num_gates(small)
+    n_gates = osv.num_gates(text)
+    threads = osv.max_threads()
+    buf = np.empty(1 << n_small, dtype=np.complex128)
+    t0 = time.perf_counter()
+    osv.simulate(small, max_gates=0, out=buf)
+    t_init = time.perf_counter() - t0
+    g = 8
+    while True:
+        t0 = time.perf_counter()
+        osv.simulate(small, max_gates=g, out=buf)
+        dt = time.perf_counter() - t0 - t_init
+        if dt * 2 > budget_s or g >= n_gates_small:
+            break
+        g = min(n_gates_small, g * 2)
+    per_gate_53 = max(dt, 1e-9) / g * 2.0 ** (53 - n_small)
+    t_full = per_gate_53 * n_gates
+    return {"value": (1 << o) / t_full, "unit": "amplitudes/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 state vector of the first {n_small} qubits over {g} gates ({dt:.1f} s), per-gate time "
+                      f"scaled by 2^{53 - n_small} to 53 qubits and by {n_gates} gates (extrapolated, {t_full:.3g} s "
+                      f"per 2^{o}-amplitude batch at fidelity 1; the GPU share time is {share_s:.3g} s at F = 2^-18)"}
 
 
 def run_serve(args, torch):
@@ -393,7 +648,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="mid", choices=["tiny", "mid", "precision", "large"])
+    ap.add_argument("--config", default="large", choices=["tiny", "mid", "precision", "large"])
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path-trials", type=int, default=None,
@@ -401,7 +656,10 @@ def main():
     ap.add_argument("--path-seed", type=int, default=0)
     ap.add_argument("--autotune", type=int, default=4,
                     help="time this many of the best estimated trees on the GPU and keep the fastest")
-    ap.add_argument("--large-prefix", type=int, default=16)
+    ap.add_argument("--large-group", type=int, default=32,
+                    help="slices of the 53-qubit share per step (the share is 1024 slices)")
+    ap.add_argument("--large-seeds", type=int, default=LARGE_SEEDS,
+                    help="tree-search seeds for the 53-qubit plan (best estimated job time kept)")
     ap.add_argument("--target-fidelity", type=float, default=0.0)
     ap.add_argument("--partial-sliced", type=int, default=12)
     ap.add_argument("--serve", action="store_true")
@@ -411,7 +669,7 @@ def main():
                     help="skip the global-cache measurement reported beside the headline value")
     args = ap.parse_args()
     if args.path_trials is None:
-        args.path_trials = {"tiny": 256, "large": 4096}.get(args.config, 65536)
+        args.path_trials = {"tiny": 256, "large": LARGE_TRIALS}.get(args.config, 65536)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sliced contraction would shard "
               "by slice range across GPUs, which this build does not run.", file=sys.stderr)

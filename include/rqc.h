@@ -15,11 +15,18 @@
  *   Handles are opaque and owned by the caller (create/destroy pairs).  All
  *   data buffers are owned by the caller.  "device" pointers are HIP device
  *   addresses on the current device; "host" pointers are ordinary memory.  The
- *   library allocates only its plan workspace (leaf tensors, intermediate arena,
- *   FP64 accumulators), through the allocator in rqc_plan_opts or hipMalloc.
+ *   library allocates its plan workspace (leaf tensors, intermediate arena,
+ *   FP64 accumulators, the norm network of partial slicing) at plan creation,
+ *   through the allocator in rqc_plan_opts or hipMalloc, and nothing per call.
+ *   The entry points without a plan (rqc_rejection_sample, rqc_kernel_cgemm)
+ *   keep a small device scratch block per (device, stream) that grows when a
+ *   call needs more and is kept until the library is unloaded; calls on one
+ *   stream are serialised on it, calls on different streams overlap.
  *   Calls that take a stream enqueue their GPU work on it and return; unless a
  *   call says otherwise, results are ready when that stream is synchronised.
  *   A plan may be used by one thread at a time; distinct plans are independent.
+ *   Successive calls on one plan may use different streams: each call's work
+ *   waits for the previous call's (the calls share the plan's workspace).
  *
  * Errors
  *   Every call returns an rqc_status.  On a non-OK status nothing was written to
@@ -91,6 +98,11 @@ typedef struct {
        <= 0: full slicing.  Otherwise k0 = ceil(3 - log2 f) partially sliced
        vertices are chosen by SlicedVertexSelect among the sliced legs, their
        norms R are computed on the GPU and X is the minimal top-R set reaching f.
+       When the library searches the slicing itself (no user path or legs), it
+       first takes k0 vertices as close to the inputs as possible (light cones of
+       at most four vertices, pairwise causally unrelated, those indexing the
+       most contraction cost first: Sec. I.B step 1), searches the tree for the
+       network with them projected, and adds legs for the memory target.
        partial_k > 0 overrides k0; partial_count > 0 keeps exactly that many
        top-R indices instead of the sum rule. */
     double target_fidelity;
@@ -105,7 +117,9 @@ typedef struct {
     /* 1 = time every kernel class with HIP events (see rqc_plan_profile). */
     int32_t profile;
     /* 1 = plan on the host only: no device is touched and the plan can only be
-       inspected (rqc_plan_info and friends), not executed. */
+       inspected (rqc_plan_info and friends), not executed.  With partial
+       slicing, S is selected but the norms R need the GPU: R and X stay empty,
+       the fidelity is reported as 0 and the default slice list is empty. */
     int32_t dry_run;
     /* Workspace allocator (NULL alloc = hipMalloc / hipFree). */
     rqc_alloc_fn alloc;
@@ -185,6 +199,24 @@ enum {
     RQC_K_CLASSES = 8
 };
 
+/* Per-op totals of the profiled launches (rqc_plan_profile_ops). */
+typedef struct {
+    int32_t cls;        /* RQC_K_* class */
+    int32_t op;         /* index of the op in the plan's launch program; -1 for
+                           the per-slice-group launches outside it (leaf
+                           selection, accumulation, normalisation) */
+    int64_t launches;
+    double seconds;     /* summed HIP-event durations */
+    double flops;       /* algorithmic flops, 8 per complex multiply-add */
+    double bytes;       /* algorithmic HBM bytes: operands read once, result
+                           written once */
+    double exec_flops;  /* flops the launches execute on the matrix cores or
+                           vector ALUs (the FP32 GEMM: 6 per complex
+                           multiply-add; the split GEMMs: 24) */
+    int32_t exec_kind;  /* precision of exec_flops: 0 = FP32, 1 = bf16/fp16 */
+    int32_t pad;
+} rqc_op_profile_t;
+
 typedef struct {
     int64_t launches[RQC_K_CLASSES];
     double seconds[RQC_K_CLASSES];   /* summed HIP-event durations */
@@ -242,6 +274,10 @@ rqc_status rqc_plan_partial(const rqc_plan *p, int32_t *S, int32_t capS, uint64_
 rqc_status rqc_plan_slices(const rqc_plan *p, uint64_t *ids, int64_t cap, int64_t *count);
 rqc_status rqc_plan_profile(const rqc_plan *p, rqc_profile_t *out);
 rqc_status rqc_plan_profile_reset(rqc_plan *p);
+/* The same profile split by op of the launch program (host array of cap
+   records; *count receives the number of records).  Synchronises on the
+   profiled work. */
+rqc_status rqc_plan_profile_ops(const rqc_plan *p, rqc_op_profile_t *ops, int32_t cap, int32_t *count);
 /* Free a plan.  No work using the plan may still be pending on any stream when
    its workspace came from a caller-supplied allocator; with the default
    allocator the device is synchronised first. */
@@ -317,7 +353,8 @@ rqc_status rqc_kernel_cgemm(const void *A, const void *B, void *C, int64_t batch
 /*
  * Bit permutation of a 2^r-element complex64 tensor (device):
  * dst[sum_i bit_i(x) << perm[i]] = src[x]; perm (host) is a permutation of 0..r-1.
- * Asynchronous on hip_stream.
+ * Asynchronous on hip_stream (the tiling descriptor is passed in the kernel
+ * arguments; perm may be reused as soon as the call returns).
  */
 rqc_status rqc_kernel_permute(const void *src, void *dst, int32_t r, const int32_t *perm, void *hip_stream);
 

@@ -111,6 +111,70 @@ def norms_R(text: str, S, nthreads: int = 0) -> np.ndarray:
     return R
 
 
+def norms_R_lightcone(text: str, S) -> np.ndarray:
+    """R[i] = ||psi_i||^2 from the light cone C_1 of S alone (Sec. I.A: the gates
+    after the cut cancel, ||psi_i||^2 = sum_j |<ji|C_1|0>|^2).  C_1 splits into
+    parts that share no qubit; C_1|0> is the tensor product of the parts' states,
+    so R is the product of the parts' norm tables.  Each part is a small state
+    vector over its own qubits: its gates in circuit order, each S-variable
+    projected onto its bit right after the gate that creates it (the
+    projection of sv.py).  For S near the inputs this reaches 53-qubit circuits."""
+    from . import small
+    c = parse(text)
+    lc = LightCones(c)
+    S = sorted(S)
+    k = len(S)
+    gates = sorted(set().union(*[lc.gates(v) for v in S])) if S else []
+    # qubit carrying each created variable (the gate's qubit for a 1q gate)
+    var_qubit = {v: q for v, gi, q in c.variables() if gi >= 0}
+    # parts: qubits joined by two-qubit gates of C_1 (union-find)
+    parent = {}
+
+    def find(q):
+        parent.setdefault(q, q)
+        while parent[q] != q:
+            parent[q] = parent[parent[q]]
+            q = parent[q]
+        return q
+
+    for gi in gates:
+        qs = c.gates[gi].qubits
+        for q in qs:
+            find(q)
+        if len(qs) == 2:
+            parent[find(qs[0])] = find(qs[1])
+    parts = {}
+    for gi in gates:
+        parts.setdefault(find(c.gates[gi].qubits[0]), []).append(gi)
+    R = np.ones(1 << k, dtype=np.float64)
+    idx = np.arange(1 << k)
+    for root, pg in parts.items():
+        qubits = sorted({q for gi in pg for q in c.gates[gi].qubits})
+        local = {q: t for t, q in enumerate(qubits)}
+        mem = [t for t, v in enumerate(S) if lc.creator[v] in set(pg)]
+        nq = len(qubits)
+        table = np.empty(1 << len(mem))
+        for bits in range(1 << len(mem)):
+            proj = {lc.creator[S[t]]: (local[var_qubit[S[t]]], (bits >> j) & 1) for j, t in enumerate(mem)}
+            psi = np.zeros((2,) * nq, dtype=np.complex128)
+            psi[(0,) * nq] = 1.0
+            for gi in pg:
+                g = c.gates[gi]
+                lg = type(g)(g.name, tuple(local[q] for q in g.qubits), g.theta, g.phi)
+                psi = small._apply(psi, nq, lg, g.matrix())
+                if gi in proj:
+                    q, b = proj[gi]
+                    sl = [slice(None)] * nq
+                    sl[nq - 1 - q] = 1 - b
+                    psi[tuple(sl)] = 0.0
+            table[bits] = float(np.vdot(psi, psi).real)
+        sub_index = np.zeros(1 << k, dtype=np.int64)
+        for j, t in enumerate(mem):
+            sub_index |= ((idx >> t) & 1) << j
+        R *= table[sub_index]
+    return R
+
+
 def select_slices(R: np.ndarray, f: float):
     """Alg. 1's last steps: sort R descending (ties: ascending index), take the
     minimal prefix whose sum reaches f; all of them if rounding never reaches f.

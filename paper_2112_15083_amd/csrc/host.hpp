@@ -106,6 +106,12 @@ struct LightCones {
 };
 LightCones light_cones(const Network &net);
 std::vector<int> sliced_vertex_select(const LightCones &lc, const std::vector<int> &I, int k);
+// Sec. I.B step 1: up to k vertices as close to the inputs as possible (light
+// cone of at most cone_max vertices), pairwise outside each other's cones (so
+// that they lie on one cut of the circuit), chosen by how much of tree t's
+// contraction cost they index (largest first; ties by ascending id).
+std::vector<int> near_input_select(const Tree &t, const std::vector<Legs> &legs, int n_vars,
+                                   const std::vector<char> &forbidden, const LightCones &lc, int k, size_t cone_max);
 
 // ------------------------------------------------------------------ lowered program
 enum OpKind { OP_SMALL = 0, OP_STREAM = 1, OP_PERMUTE = 2, OP_GEMM = 3 };
@@ -294,7 +300,14 @@ struct PlanCore {
 };
 
 // Contraction tree and sliced legs (user path/legs or the randomised search).
-void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std::vector<int> *user_sliced);
+// With partial slicing (lc non-null, no user path or legs), the searched
+// slicing starts with k0 near-input vertices (near_input_select on the best
+// tree of a first search), and the tree is searched again on the network with
+// those vertices projected; the memory slicing then adds legs to them.
+void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std::vector<int> *user_sliced,
+               const LightCones *lc = nullptr);
+// k0 of Alg. 1: ceil(3 - log2 f), or opts.partial_k when set.
+int partial_k0(const rqc_plan_opts &o);
 // Appendix B, Alg. 1: S by SlicedVertexSelect, R from `norms` (which contracts
 // the doubled network), X and F.
 void plan_partial(PlanCore &p, const Network &net,

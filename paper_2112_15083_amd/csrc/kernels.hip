@@ -902,10 +902,8 @@ PermDesc make_perm_desc(int r, const std::vector<int> &perm) {
 // One tile (at most 1024 elements) per iteration: read in source order
 // (coalesced on the low source bits), write in destination order (coalesced on
 // the low destination bits) through a padded LDS tile.
-__global__ void __launch_bounds__(256) k_permute(const PermDesc *__restrict__ dp, const float2 *__restrict__ src,
-                                                 float2 *__restrict__ dst) {
-    __shared__ float2 tile[1024 + 32];
-    const PermDesc &d = *dp;
+__device__ __forceinline__ void permute_tiles(const PermDesc &d, const float2 *__restrict__ src,
+                                              float2 *__restrict__ dst, float2 *tile) {
     const int n = 1 << d.tile_log;
     const int tid = threadIdx.x;
     int64_t rd[4], wd[4];
@@ -935,10 +933,28 @@ __global__ void __launch_bounds__(256) k_permute(const PermDesc *__restrict__ dp
     }
 }
 
+// descriptor in device memory (plans upload theirs once)
+__global__ void __launch_bounds__(256) k_permute(const PermDesc *__restrict__ dp, const float2 *__restrict__ src,
+                                                 float2 *__restrict__ dst) {
+    __shared__ float2 tile[1024 + 32];
+    permute_tiles(*dp, src, dst, tile);
+}
+
+// descriptor passed by value in the kernel arguments (no device copy needed)
+__global__ void __launch_bounds__(256) k_permute_v(const PermDesc d, const float2 *__restrict__ src,
+                                                   float2 *__restrict__ dst) {
+    __shared__ float2 tile[1024 + 32];
+    permute_tiles(d, src, dst, tile);
+}
+
+static unsigned permute_blocks(int64_t n_tiles) { return (unsigned)std::min<int64_t>(n_tiles, 256 * 32); }
+
 void launch_permute(const PermDesc *d_desc, int64_t n_tiles, const float2 *src, float2 *dst, hipStream_t s) {
-    int64_t blocks = n_tiles;
-    if (blocks > 256 * 32) blocks = 256 * 32;
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s, d_desc, src, dst);
+    hipLaunchKernelGGL(k_permute, dim3(permute_blocks(n_tiles)), dim3(256), 0, s, d_desc, src, dst);
+}
+
+void launch_permute_value(const PermDesc &d, const float2 *src, float2 *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_permute_v, dim3(permute_blocks(d.n_tiles)), dim3(256), 0, s, d, src, dst);
 }
 
 // ------------------------------------------------------------------ complex GEMM, FP32 MFMA

@@ -47,6 +47,8 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
                    float2 *w, const float2 *b2, hipStream_t s);
 // d_desc: the permute descriptor in device memory
 void launch_permute(const PermDesc *d_desc, int64_t n_tiles, const float2 *src, float2 *dst, hipStream_t s);
+// the same with the descriptor in the kernel arguments
+void launch_permute_value(const PermDesc &d, const float2 *src, float2 *dst, hipStream_t s);
 // precision: rqc_precision; amax: two device words of scratch (fp16 scaling)
 void launch_gemm(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s);
 // d_maps[0]: open index -> root offset, d_maps[1]: batched slice index -> root offset
@@ -56,13 +58,14 @@ void launch_zero(double2 *acc, int64_t n, hipStream_t s);
 void launch_finalize(const double2 *acc, int64_t n, double scale, float2 *out, double2 *out64,
                      hipStream_t s);
 
-// sampler
-struct SampleOut {
-    uint64_t bits;
-};
-hipError_t run_sampler(const float2 *amps, const uint64_t *d_fixed, int64_t n_batches, const int32_t *d_open,
+// sampler: `scratch` is device memory of at least sampler_scratch_bytes(items,
+// batches, n_open) bytes, where items = pick_steps in pick mode, else
+// n_batches * 2^(n_open - log2_na); fixed and open_q are host arrays.  The
+// call synchronises s before returning.
+size_t sampler_scratch_bytes(int64_t n_items, int64_t n_batches, int n_open);
+hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batches, const int32_t *open_q,
                        int n_open, int log2_na, int n_qubits, double alpha, double f_norm, uint64_t seed,
                        uint64_t base, int64_t pick_steps, int64_t n_samples, uint64_t *out,
-                       int64_t *n_out, rqc_sample_stats *stats, hipStream_t s);
+                       int64_t *n_out, rqc_sample_stats *stats, void *scratch, hipStream_t s);
 
 } // namespace rqc

@@ -154,7 +154,12 @@ double estimate_seconds(const PlanCore &p) {
     return t * (double)std::max<int64_t>(1, p.info.n_groups);
 }
 
-void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std::vector<int> *user_sliced) {
+int partial_k0(const rqc_plan_opts &o) {
+    return o.partial_k > 0 ? o.partial_k : (int)std::ceil(3.0 - std::log2(o.target_fidelity));
+}
+
+void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std::vector<int> *user_sliced,
+               const LightCones *lc) {
     const NetSpec &sp = p.spec;
     const int nv = sp.n_vars;
     std::vector<char> kept(nv, 0), fixed(nv, 0);
@@ -191,9 +196,66 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
         }
     } else {
         int trials = p.opts.path_trials > 0 ? p.opts.path_trials : 16;
-        std::vector<SearchResult> rs = search_tree(path_legs, nv, kept, sp.forbidden, user_sliced,
-                                                   p.opts.max_log2_tensor, p.opts.n_sliced_target, trials,
-                                                   p.opts.path_seed);
+        std::vector<SearchResult> rs;
+        if (lc && !user_sliced) {
+            // partial slicing: S near the inputs first (Sec. I.B step 1), then
+            // the tree for the network with S projected, then memory slicing
+            std::vector<SearchResult> first = search_tree(path_legs, nv, kept, sp.forbidden, nullptr,
+                                                          p.opts.max_log2_tensor, p.opts.n_sliced_target,
+                                                          std::max(16, trials / 4), p.opts.path_seed);
+            std::vector<char> none(nv, 0);
+            // one candidate S from each of the best first trees (they differ in
+            // which near-input legs carry the most cost); each gets its own
+            // search, and all results compete below
+            std::vector<std::vector<int>> tried;
+            const int n_first = std::min<int>(4, (int)first.size());
+            for (int fi = 0; fi < n_first; fi++) {
+                auto legs_first = tree_legs(first[fi].tree, path_legs, nv, none, kept);
+                // cones of at most 4 vertices: outputs of the first two
+                // single-qubit layers in this gate set
+                std::vector<int> S0 = near_input_select(first[fi].tree, legs_first, nv, sp.forbidden, *lc,
+                                                        partial_k0(p.opts), 4);
+                std::vector<int> key(S0);
+                std::sort(key.begin(), key.end());
+                if (std::find(tried.begin(), tried.end(), key) != tried.end()) continue;
+                tried.push_back(key);
+                std::vector<char> inS(nv, 0), forb(sp.forbidden);
+                for (int v : S0) inS[v] = 1, forb[v] = 1;
+                std::vector<Legs> reduced;
+                for (auto &l : path_legs) {
+                    Legs m;
+                    for (int v : l)
+                        if (!inS[v]) m.push_back(v);
+                    reduced.push_back(m);
+                }
+                std::vector<SearchResult> part =
+                    search_tree(reduced, nv, kept, forb, nullptr, p.opts.max_log2_tensor, p.opts.n_sliced_target,
+                                std::max(16, trials / n_first), p.opts.path_seed + 1 + (uint64_t)fi);
+                for (auto &r : part) {
+                    r.sliced.insert(r.sliced.begin(), S0.begin(), S0.end());
+                    r.log2cost += (double)S0.size();
+                    rs.push_back(std::move(r));
+                }
+            }
+            std::stable_sort(rs.begin(), rs.end(),
+                             [](const SearchResult &a, const SearchResult &b) { return a.log2cost < b.log2cost; });
+        } else if (user_sliced) {
+            // the tree for the network with the given legs projected
+            std::vector<char> inI(nv, 0);
+            for (int v : *user_sliced) inI[v] = 1;
+            std::vector<Legs> reduced;
+            for (auto &l : path_legs) {
+                Legs m;
+                for (int v : l)
+                    if (!inI[v]) m.push_back(v);
+                reduced.push_back(m);
+            }
+            rs = search_tree(reduced, nv, kept, sp.forbidden, user_sliced, p.opts.max_log2_tensor,
+                             p.opts.n_sliced_target, trials, p.opts.path_seed);
+        } else {
+            rs = search_tree(path_legs, nv, kept, sp.forbidden, nullptr, p.opts.max_log2_tensor,
+                             p.opts.n_sliced_target, trials, p.opts.path_seed);
+        }
         // the best by the proxy cost are lowered and compared by estimated time
         // (with the global cache, the per-batch time the proxy does not see)
         const size_t n_lower = 64; // lowering a candidate costs ~10 ms
@@ -225,7 +287,7 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
 void plan_partial(PlanCore &p, const Network &net,
                   const std::function<std::vector<double>(const NetSpec &, const std::vector<int> &)> &norms) {
     const double f = p.opts.target_fidelity;
-    int k0 = p.opts.partial_k > 0 ? p.opts.partial_k : (int)std::ceil(3.0 - std::log2(f));
+    const int k0 = partial_k0(p.opts);
     LightCones lc = light_cones(net);
     std::vector<int> S = sliced_vertex_select(lc, p.sliced, k0);
     if (S.empty()) fail(RQC_EPLAN, "no partially sliced vertex could be selected");

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -36,6 +37,43 @@ static void check_device() {
         fail(RQC_EDEVICE, std::string("librqc is built for gfx950; current device is ") + prop.gcnArchName);
 }
 
+// Device scratch for the entry points that have no plan (the sampler and the
+// kernel-level primitives): one block per (device, stream), grown
+// geometrically with hipMalloc when a call needs more and never freed while
+// the library is loaded (retired blocks are kept rather than freed, since
+// hipFree waits for the whole device).  A call holds its block's lock until
+// its work on the stream no longer reads it, so concurrent calls on one stream
+// from several threads are serialised and calls on different streams overlap.
+struct StreamScratch {
+    std::mutex mu;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    std::vector<void *> retired;
+};
+
+static StreamScratch &stream_scratch(hipStream_t s) {
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, std::unique_ptr<StreamScratch>> pool;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto &e = pool[{dev, s}];
+    if (!e) e = std::make_unique<StreamScratch>();
+    return *e;
+}
+
+// Caller holds b.mu.
+static void *scratch_reserve(StreamScratch &b, size_t need) {
+    if (b.bytes >= need) return b.ptr;
+    size_t sz = std::max<size_t>(need, std::max<size_t>(2 * b.bytes, (size_t)1 << 20));
+    void *p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) fail(RQC_ENOMEM, "scratch allocation of " + std::to_string(sz) + " bytes failed");
+    if (b.ptr) b.retired.push_back(b.ptr);
+    b.ptr = p;
+    b.bytes = sz;
+    return p;
+}
+
 } // namespace rqc
 
 using namespace rqc;
@@ -46,9 +84,10 @@ struct rqc_circuit {
 };
 
 struct PendingEvent {
-    int cls;
+    int cls, op;
     hipEvent_t a, b;
-    double flops, bytes;
+    double flops, bytes, exec_flops;
+    int exec_kind;
 };
 
 struct rqc_plan : PlanCore {
@@ -67,8 +106,14 @@ struct rqc_plan : PlanCore {
     PermDesc *d_perm = nullptr;  // permute descriptors
     float2 *d_cache = nullptr;   // global cache: one block per default slice group, plus one spare
     bool cache_filled = false;
+    // ordering of calls on one plan across streams: each call waits for the
+    // previous call's work (it reuses the arena, leaf buffer, accumulator and
+    // global cache) and records its own end
+    hipEvent_t done = nullptr;
+    bool done_recorded = false;
     // profiling
     rqc_profile_t prof{};
+    std::map<std::pair<int, int>, rqc_op_profile_t> op_prof; // (class, program op) -> totals
     std::vector<PendingEvent> pending;
     std::vector<hipEvent_t> pool;
 
@@ -96,6 +141,9 @@ struct rqc_plan : PlanCore {
             }
         }
         owned.clear();
+        if (done) (void)hipEventDestroy(done);
+        done = nullptr;
+        done_recorded = false;
         for (auto &e : pool) (void)hipEventDestroy(e);
         for (auto &p : pending) (void)hipEventDestroy(p.a), (void)hipEventDestroy(p.b);
         pool.clear();
@@ -120,6 +168,15 @@ struct rqc_plan : PlanCore {
             prof.seconds[p.cls] += ms * 1e-3;
             prof.flops[p.cls] += p.flops;
             prof.bytes[p.cls] += p.bytes;
+            rqc_op_profile_t &o = op_prof[{p.cls, p.op}];
+            o.cls = p.cls;
+            o.op = p.op;
+            o.exec_kind = p.exec_kind;
+            o.launches++;
+            o.seconds += ms * 1e-3;
+            o.flops += p.flops;
+            o.bytes += p.bytes;
+            o.exec_flops += p.exec_flops;
             pool.push_back(p.a);
             pool.push_back(p.b);
         }
@@ -171,13 +228,18 @@ struct rqc_plan : PlanCore {
 
 namespace {
 
+// HIP events around one launch when profiling.  op: the program op (-1 for the
+// per-group launches outside the program); xf: flops the launch executes on
+// the matrix cores or vector ALUs (kind 0: FP32, 1: bf16/fp16).
 struct Timer {
     rqc_plan *p;
     hipStream_t s;
-    int cls;
-    double f, b;
+    int cls, op;
+    double f, b, xf;
+    int xk;
     hipEvent_t a{};
-    Timer(rqc_plan *p_, hipStream_t s_, int c, double f_, double b_) : p(p_), s(s_), cls(c), f(f_), b(b_) {
+    Timer(rqc_plan *p_, hipStream_t s_, int c, double f_, double b_, int op_ = -1, double xf_ = 0, int xk_ = 0)
+        : p(p_), s(s_), cls(c), op(op_), f(f_), b(b_), xf(xf_), xk(xk_) {
         if (p->opts.profile) {
             a = p->ev();
             HIP_OK(hipEventRecord(a, s));
@@ -187,7 +249,7 @@ struct Timer {
         if (p->opts.profile) {
             hipEvent_t e = p->ev();
             HIP_OK(hipEventRecord(e, s));
-            p->pending.push_back({cls, a, e, f, b});
+            p->pending.push_back({cls, op, a, e, f, b, xf, xk});
         }
     }
 };
@@ -287,27 +349,30 @@ float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hi
         Timer t(p, s, RQC_K_LEAF, 0, 16.0 * (double)pg.leafbuf_elems);
         launch_leaf_select(p->d_full, p->d_leafbuf, p->d_sel, (int)p->sel.size(), vals, s);
     }
-    for (const Op &op : pg.ops) {
+    for (size_t oi = 0; oi < pg.ops.size(); oi++) {
+        const Op &op = pg.ops[oi];
         if (op.kind != OP_SMALL && ((phase == RUN_INDEP && op.dep) || (phase == RUN_DEP && !op.dep))) continue;
         switch (op.kind) {
         case OP_SMALL: {
             const int n = (int)pg.small_trees.size(), ni = pg.n_small_indep;
             const int first = phase == RUN_DEP ? ni : 0, count = phase == RUN_INDEP ? ni : n - first;
-            Timer t(p, s, RQC_K_SMALL, op.flops, op.bytes);
+            Timer t(p, s, RQC_K_SMALL, op.flops, op.bytes, (int)oi, op.flops, 0);
             launch_small_trees(p->d_steps, p->d_trees + first, count, pg.small_lds_elems, p->d_leafbuf, p->d_arena,
                                cache, s);
             break;
         }
         case OP_STREAM: {
             const StreamOp &so = pg.streams[op.index];
-            Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes);
+            // the matrix-core forms multiply by B's real block form: 8 real
+            // flops per complex multiply-add, as counted; the vector forms the same
+            Timer t(p, s, RQC_K_STREAM, op.flops, op.bytes, (int)oi, op.flops, 0);
             launch_stream(so, p->d_smaps + (size_t)op.index * SM_COUNT, ptr(so.a), ptr(so.b), ptr(so.c),
                           so.lk && so.lk_split > 0 ? ptr(so.w) : nullptr, so.mx2 ? ptr(so.b2) : nullptr, s);
             break;
         }
         case OP_PERMUTE: {
             const PermuteOp &po = pg.permutes[op.index];
-            Timer t(p, s, RQC_K_PERMUTE, op.flops, op.bytes);
+            Timer t(p, s, RQC_K_PERMUTE, op.flops, op.bytes, (int)oi, 0, 0);
             launch_permute(p->d_perm + op.index, p->perm_desc[op.index].n_tiles, ptr(po.src), ptr(po.dst), s);
             break;
         }
@@ -328,7 +393,10 @@ float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hi
             ga.b_nfast = go.b_nfast;
             ga.ksplit = go.ksplit;
             ga.W = go.ksplit > 1 ? ptr(go.w) : nullptr;
-            Timer t(p, s, RQC_K_GEMM, op.flops, op.bytes);
+            // executed: three FP32 real products per complex multiply-add, or
+            // three bf16/fp16 products of the 2K-long real view per output part
+            const bool split = p->opts.precision != RQC_C64 && go.K >= 16;
+            Timer t(p, s, RQC_K_GEMM, op.flops, op.bytes, (int)oi, (split ? 3.0 : 0.75) * op.flops, split ? 1 : 0);
             launch_gemm(ga, p->opts.precision, p->d_amax, s);
             break;
         }
@@ -349,6 +417,8 @@ void execute(rqc_plan *p, const GroupList &groups, bool is_default, const uint64
     const double scale = p->kappa / std::sqrt(p->F);
     const int nfix = (int)p->spec.fixed_vars.size();
     const bool cached = pg.cache && is_default;
+    if (!p->done) HIP_OK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+    if (p->done_recorded) HIP_OK(hipStreamWaitEvent(s, p->done, 0));
     auto projection = [&](uint64_t fixed, uint64_t g) {
         ProjVals vals{};
         for (int i = 0; i < nfix; i++)
@@ -386,6 +456,8 @@ void execute(rqc_plan *p, const GroupList &groups, bool is_default, const uint64
         }
     }
     HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(p->done, s));
+    p->done_recorded = true;
     if (p->opts.profile && p->pending.size() > 8192) p->flush_profile();
 }
 
@@ -449,26 +521,15 @@ std::vector<double> gpu_norms(const rqc_plan_opts &outer, const NetSpec &spec, c
     HIP_OK(hipGetDevice(&q.device));
     q.upload();
     const size_t n = (size_t)1 << S.size();
-    float2 *amps = nullptr;
-    double2 *r64 = nullptr;
-    HIP_OK(hipMalloc(&amps, n * sizeof(float2)));
-    hipError_t e = hipMalloc(&r64, n * sizeof(double2));
-    if (e != hipSuccess) {
-        (void)hipFree(amps);
-        fail(RQC_ENOMEM, "norm tensor allocation failed");
-    }
+    // output buffers from the norm plan's workspace (the caller's allocator
+    // when one is given), released with that plan
+    float2 *amps = (float2 *)q.dalloc(n * sizeof(float2));
+    double2 *r64 = (double2 *)q.dalloc(n * sizeof(double2));
     std::vector<double2> host(n);
-    try {
-        uint64_t zero = 0;
-        execute(&q, default_groups(&q), true, &zero, 1, amps, r64, nullptr);
-        HIP_OK(hipMemcpy(host.data(), r64, n * sizeof(double2), hipMemcpyDeviceToHost));
-    } catch (...) {
-        (void)hipFree(amps);
-        (void)hipFree(r64);
-        throw;
-    }
-    (void)hipFree(amps);
-    (void)hipFree(r64);
+    uint64_t zero = 0;
+    execute(&q, default_groups(&q), true, &zero, 1, amps, r64, nullptr);
+    HIP_OK(hipMemcpy(host.data(), r64, n * sizeof(double2), hipMemcpyDeviceToHost));
+    HIP_OK(hipStreamSynchronize(nullptr));
     std::vector<double> R(n);
     for (size_t i = 0; i < n; i++) R[i] = host[i].x;
     return R;
@@ -518,7 +579,7 @@ rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_
         if (p.opts.precision < 0 || p.opts.precision > 2) fail(RQC_EINVAL, "unknown precision");
         const double f = p.opts.target_fidelity;
         const bool partial = f > 0 && f < 1;
-        if (partial && p.opts.dry_run) fail(RQC_EINVAL, "partial slicing computes its norms on the GPU");
+
         if (!p.opts.dry_run) {
             check_device();
             HIP_OK(hipGetDevice(&p.device));
@@ -528,7 +589,9 @@ rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_
         p.info.n_qubits = c->c.n;
         std::vector<int> user;
         if (sliced_legs) user.assign(sliced_legs, sliced_legs + n_sliced);
-        plan_tree(p, path, n_path_pairs, sliced_legs ? &user : nullptr);
+        std::unique_ptr<LightCones> lc;
+        if (partial && !path && !sliced_legs) lc = std::make_unique<LightCones>(light_cones(c->net));
+        plan_tree(p, path, n_path_pairs, sliced_legs ? &user : nullptr, lc.get());
         // time the best candidates on the device (skipping any estimated over
         // 2 s); another tree replaces the estimate's choice only if it is at
         // least 5 % faster, so that timing noise does not change the plan
@@ -544,7 +607,11 @@ rqc_status rqc_plan_create(const rqc_circuit *c, const int32_t *path, int32_t n_
             p.tree = p.candidates[best].tree;
             p.sliced = p.candidates[best].sliced;
         }
-        if (partial) {
+        if (partial && p.opts.dry_run) {
+            // the norms need the GPU: a host-only plan selects S and stops there
+            p.S = sliced_vertex_select(light_cones(c->net), p.sliced, partial_k0(p.opts));
+            p.F = 0;
+        } else if (partial) {
             rqc_plan_opts o = p.opts;
             plan_partial(p, c->net, [&](const NetSpec &ds, const std::vector<int> &S) { return gpu_norms(o, ds, S); });
         }
@@ -626,6 +693,21 @@ rqc_status rqc_plan_profile_reset(rqc_plan *p) {
         if (!p) fail(RQC_EINVAL, "null plan");
         p->flush_profile();
         p->prof = rqc_profile_t{};
+        p->op_prof.clear();
+    });
+}
+
+rqc_status rqc_plan_profile_ops(const rqc_plan *pc, rqc_op_profile_t *ops, int32_t cap, int32_t *count) {
+    return guard([&] {
+        if (!pc || !count) fail(RQC_EINVAL, "null argument");
+        rqc_plan *p = const_cast<rqc_plan *>(pc);
+        p->flush_profile();
+        *count = (int32_t)p->op_prof.size();
+        int32_t k = 0;
+        for (auto &kv : p->op_prof) {
+            if (!ops || k >= cap) break;
+            ops[k++] = kv.second;
+        }
     });
 }
 
@@ -703,27 +785,13 @@ rqc_status rqc_rejection_sample(const void *amps, const uint64_t *fixed_bits, in
         for (int b = 0; b < n_open; b++)
             if (open_qubits[b] < 0 || open_qubits[b] >= n_qubits) fail(RQC_EINVAL, "open qubit out of range");
         hipStream_t s = (hipStream_t)hip_stream;
-        std::vector<uint64_t> fb(std::max<int64_t>(n_batches, 1), 0);
-        for (int64_t i = 0; i < n_batches; i++) fb[i] = fixed_bits[i];
-        std::vector<int32_t> oq(std::max(n_open, 1), 0);
-        for (int b = 0; b < n_open; b++) oq[b] = open_qubits[b];
-        uint64_t *d_fixed = nullptr;
-        int32_t *d_open = nullptr;
-        HIP_OK(hipMalloc(&d_fixed, fb.size() * sizeof(uint64_t)));
-        hipError_t e = hipMalloc(&d_open, oq.size() * sizeof(int32_t));
-        if (e != hipSuccess) {
-            (void)hipFree(d_fixed);
-            fail(RQC_EDEVICE, "hipMalloc failed");
-        }
-        e = hipMemcpyAsync(d_fixed, fb.data(), fb.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_open, oq.data(), oq.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = run_sampler((const float2 *)amps, d_fixed, n_batches, d_open, n_open, log2_NA, n_qubits, alpha,
-                            F_norm, seed, batch_index_base, pick_steps, n_samples, out_samples, n_out, stats, s);
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(d_fixed);
-        (void)hipFree(d_open);
+        const int64_t items = pick_steps > 0 ? pick_steps : n_batches * ((int64_t)1 << (n_open - log2_NA));
+        StreamScratch &sc = stream_scratch(s);
+        std::lock_guard<std::mutex> lk(sc.mu);
+        void *w = scratch_reserve(sc, sampler_scratch_bytes(items, n_batches, n_open));
+        const hipError_t e = run_sampler((const float2 *)amps, fixed_bits, n_batches, open_qubits, n_open, log2_NA,
+                                         n_qubits, alpha, F_norm, seed, batch_index_base, pick_steps, n_samples,
+                                         out_samples, n_out, stats, w, s);
         if (e != hipSuccess) fail(RQC_EDEVICE, std::string("sampler: ") + hipGetErrorString(e));
     });
     if (st == RQC_OK && *n_out < n_samples) {
@@ -731,18 +799,6 @@ rqc_status rqc_rejection_sample(const void *amps, const uint64_t *fixed_bits, in
         return RQC_ESHORT;
     }
     return st;
-}
-
-static unsigned *kernel_amax_scratch() {
-    // two words per device for the fp16 split scaling of rqc_kernel_cgemm
-    static std::mutex mu;
-    static std::vector<unsigned *> per_dev;
-    std::lock_guard<std::mutex> lk(mu);
-    int dev = 0;
-    HIP_OK(hipGetDevice(&dev));
-    if ((int)per_dev.size() <= dev) per_dev.resize(dev + 1, nullptr);
-    if (!per_dev[dev]) HIP_OK(hipMalloc(&per_dev[dev], 256));
-    return per_dev[dev];
 }
 
 rqc_status rqc_kernel_cgemm(const void *A, const void *B, void *C, int64_t batch, int64_t M, int64_t N, int64_t K,
@@ -768,7 +824,12 @@ rqc_status rqc_kernel_cgemm(const void *A, const void *B, void *C, int64_t batch
         g.sc = M * N;
         g.a_kfast = a_kfast ? 1 : 0;
         g.b_nfast = b_nfast ? 1 : 0;
-        launch_gemm(g, precision, kernel_amax_scratch(), (hipStream_t)hip_stream);
+        hipStream_t s = (hipStream_t)hip_stream;
+        // the fp16 scaling maxima: two words of this stream's scratch, written
+        // and read in stream order
+        StreamScratch &sc = stream_scratch(s);
+        std::lock_guard<std::mutex> lk(sc.mu);
+        launch_gemm(g, precision, (unsigned *)scratch_reserve(sc, 256), s);
         HIP_OK(hipGetLastError());
     });
 }
@@ -786,21 +847,9 @@ rqc_status rqc_kernel_permute(const void *src, void *dst, int32_t r, const int32
         }
         check_device();
         PermDesc d = make_perm_desc(r, pv);
-        // descriptor in device memory, one slot per device; the copy is ordered
-        // on the caller's stream before the kernel that reads it
-        static std::mutex mu;
-        static std::vector<PermDesc *> slot;
-        std::lock_guard<std::mutex> lk(mu);
-        int dev = 0;
-        HIP_OK(hipGetDevice(&dev));
-        if ((int)slot.size() <= dev) slot.resize(dev + 1, nullptr);
-        if (!slot[dev]) HIP_OK(hipMalloc(&slot[dev], sizeof(PermDesc)));
-        hipStream_t s = (hipStream_t)hip_stream;
-        HIP_OK(hipStreamSynchronize(s));
-        HIP_OK(hipMemcpy(slot[dev], &d, sizeof(d), hipMemcpyHostToDevice));
-        launch_permute(slot[dev], d.n_tiles, (const float2 *)src, (float2 *)dst, s);
+        // the descriptor travels in the kernel arguments
+        launch_permute_value(d, (const float2 *)src, (float2 *)dst, (hipStream_t)hip_stream);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipStreamSynchronize(s));
     });
 }
 

@@ -10,7 +10,7 @@
 // Accepted samples are compacted in ascending batch (or step) order.
 #include <hip/hip_runtime.h>
 
-#include <mutex>
+#include <algorithm>
 
 #include "kernels.hpp"
 
@@ -173,47 +173,53 @@ __global__ void __launch_bounds__(1024) k_compact(const SubResult *__restrict__ 
     }
 }
 
-static std::mutex g_scratch_mu;
-static void *g_scratch = nullptr;
-static size_t g_scratch_bytes = 0;
-static int g_scratch_dev = -1;
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-hipError_t run_sampler(const float2 *amps, const uint64_t *d_fixed, int64_t n_batches, const int32_t *d_open,
+// Scratch layout of one call: per-item results, the batches' fixed bits, the
+// open qubits, the statistics (each 256-byte aligned).
+size_t sampler_scratch_bytes(int64_t n_items, int64_t n_batches, int n_open) {
+    return align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SubResult)) +
+           align256((size_t)std::max<int64_t>(n_batches, 1) * sizeof(uint64_t)) +
+           align256((size_t)std::max(n_open, 1) * sizeof(int32_t)) + align256(sizeof(CompactStats));
+}
+
+hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batches, const int32_t *open_q,
                        int n_open, int log2_na, int n_qubits, double alpha, double f_norm, uint64_t seed,
                        uint64_t base, int64_t pick_steps, int64_t n_samples, uint64_t *out, int64_t *n_out,
-                       rqc_sample_stats *stats, hipStream_t s) {
-    std::lock_guard<std::mutex> lk(g_scratch_mu);
+                       rqc_sample_stats *stats, void *scratch, hipStream_t s) {
     const int pick = pick_steps > 0;
     const int64_t sub_per_batch = (int64_t)1 << (n_open - log2_na);
     const int64_t n_items = pick ? pick_steps : n_batches * sub_per_batch;
     const int log2_nb = n_qubits - log2_na;
-    const size_t need = (size_t)n_items * sizeof(SubResult) + sizeof(CompactStats) + 256;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (g_scratch_bytes < need || g_scratch_dev != dev) {
-        if (g_scratch) (void)hipFree(g_scratch);
-        g_scratch = nullptr;
-        g_scratch_bytes = 0;
-        e = hipMalloc(&g_scratch, need);
-        if (e != hipSuccess) return e;
-        g_scratch_bytes = need;
-        g_scratch_dev = dev;
-    }
-    SubResult *res = (SubResult *)g_scratch;
-    CompactStats *cst = (CompactStats *)((char *)g_scratch + (((size_t)n_items * sizeof(SubResult) + 255) & ~255ull));
+    char *w = (char *)scratch;
+    SubResult *res = (SubResult *)w;
+    w += align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SubResult));
+    uint64_t *d_fixed = (uint64_t *)w;
+    w += align256((size_t)std::max<int64_t>(n_batches, 1) * sizeof(uint64_t));
+    int32_t *d_open = (int32_t *)w;
+    w += align256((size_t)std::max(n_open, 1) * sizeof(int32_t));
+    CompactStats *cst = (CompactStats *)w;
+    // the host arrays are read by these copies before the stream is synchronised below
+    hipError_t e = hipSuccess;
+    if (n_batches > 0) e = hipMemcpyAsync(d_fixed, fixed, (size_t)n_batches * sizeof(uint64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n_open > 0)
+        e = hipMemcpyAsync(d_open, open_q, (size_t)n_open * sizeof(int32_t), hipMemcpyHostToDevice, s);
     const double c = std::ldexp(1.0, log2_nb) / (alpha * f_norm);
     const double cap = alpha / std::ldexp(1.0, log2_nb);
-    if (n_items > 0) {
+    if (e == hipSuccess && n_items > 0) {
         hipLaunchKernelGGL(k_sample_batches, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, amps,
                            n_items, log2_na, log2_nb, c, seed, base, pick, res);
     }
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, res, n_items, log2_na, sub_per_batch, d_fixed, d_open,
-                       n_open, pick, n_samples, cap, f_norm, out, cst);
-    CompactStats h;
-    e = hipMemcpyAsync(&h, cst, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, res, n_items, log2_na, sub_per_batch, d_fixed,
+                           d_open, n_open, pick, n_samples, cap, f_norm, out, cst);
+        e = hipGetLastError();
+    }
+    CompactStats h{};
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, cst, sizeof(h), hipMemcpyDeviceToHost, s);
+    // always wait: the copies above read host memory owned by the caller
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) return e;
     *n_out = h.n_out;
     if (stats) {

@@ -572,6 +572,43 @@ LightCones light_cones(const Network &net) {
     return lc;
 }
 
+std::vector<int> near_input_select(const Tree &t, const std::vector<Legs> &legs, int n_vars,
+                                   const std::vector<char> &forbidden, const LightCones &lc, int k, size_t cone_max) {
+    // weight of a variable: summed cost of the contraction steps it indexes
+    // (relative to the largest), i.e. how much projecting it saves
+    const int ns = (int)t.steps.size();
+    std::vector<Legs> un(ns);
+    double mxr = 0;
+    for (int s = 0; s < ns; s++) {
+        un[s] = merge_union(legs[t.steps[s].first], legs[t.steps[s].second]);
+        mxr = std::max(mxr, (double)un[s].size());
+    }
+    std::vector<double> w(n_vars, 0.0);
+    for (int s = 0; s < ns; s++) {
+        const double c = std::exp2((double)un[s].size() - mxr);
+        for (int v : un[s]) w[v] += c;
+    }
+    std::vector<int> cand;
+    for (int v = 0; v < n_vars; v++)
+        if (!forbidden[v] && !lc.cone_vertices[v].empty() && lc.cone_vertices[v].size() <= cone_max) cand.push_back(v);
+    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return w[a] > w[b]; });
+    std::vector<int> S;
+    for (int v : cand) {
+        if ((int)S.size() >= k) break;
+        const Legs &cv = lc.cone_vertices[v];
+        bool ok = true;
+        for (int u : S) {
+            const Legs &cu = lc.cone_vertices[u];
+            if (std::binary_search(cv.begin(), cv.end(), u) || std::binary_search(cu.begin(), cu.end(), v)) {
+                ok = false;
+                break;
+            }
+        }
+        if (ok) S.push_back(v);
+    }
+    return S;
+}
+
 std::vector<int> sliced_vertex_select(const LightCones &lc, const std::vector<int> &I, int k) {
     // Appendix B, SlicedVertexSelect: grow S greedily by the candidate whose
     // addition gives the smallest |L'_C(S u {u})|; candidates exclude the

@@ -74,6 +74,17 @@ class Profile(ctypes.Structure):
                                  bytes=self.bytes[i]) for i in range(8)}
 
 
+class OpProfile(ctypes.Structure):
+    _fields_ = [("cls", ctypes.c_int32), ("op", ctypes.c_int32), ("launches", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("exec_flops", ctypes.c_double), ("exec_kind", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d["cls"] = K_NAMES[self.cls]
+        return d
+
+
 _P = ctypes.c_void_p
 _sig = {
     "rqc_load_circuit": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_P)],
@@ -88,6 +99,7 @@ _sig = {
     "rqc_plan_slices": [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
     "rqc_plan_profile": [_P, ctypes.POINTER(Profile)],
     "rqc_plan_profile_reset": [_P],
+    "rqc_plan_profile_ops": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "rqc_contract_amplitudes": [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P],
     "rqc_kernel_cgemm": [_P, _P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
@@ -246,7 +258,7 @@ def plan_partial(p: Plan):
     k, nx = info["n_partial"], info["n_partial_kept"]
     S = (ctypes.c_int32 * max(1, k))()
     X = (ctypes.c_uint64 * max(1, nx))()
-    nr = (1 << k) if k else 0
+    nr = (1 << k) if k and nx else 0  # a host-only plan selects S but has no norms
     R = (ctypes.c_double * max(1, nr))()
     _check(_lib.rqc_plan_partial(p.handle, S, k, X, nx, R, nr))
     return list(S)[:k], list(X)[:nx], list(R)[:nr]
@@ -266,6 +278,15 @@ def plan_profile(p: Plan) -> dict:
     pr = Profile()
     _check(_lib.rqc_plan_profile(p.handle, ctypes.byref(pr)))
     return pr.as_dict()
+
+
+def plan_profile_ops(p: Plan) -> list:
+    """Per-op profile records (see rqc_op_profile_t)."""
+    n = ctypes.c_int32()
+    _check(_lib.rqc_plan_profile_ops(p.handle, None, 0, ctypes.byref(n)))
+    arr = (OpProfile * max(1, n.value))()
+    _check(_lib.rqc_plan_profile_ops(p.handle, arr, n.value, ctypes.byref(n)))
+    return [arr[i].as_dict() for i in range(n.value)]
 
 
 def plan_profile_reset(p: Plan):

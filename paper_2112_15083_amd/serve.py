@@ -4,13 +4,19 @@ Requests (a circuit, an open batch of 2^u amplitudes, optionally rejection
 samples) flow through three stages that overlap:
 
   plan     host worker threads build each request's plan (the C++ planner runs
-           outside the GIL); requests whose plan exceeds the cost cap are refused;
+           outside the GIL); the contraction tree and sliced legs depend only on
+           the circuit's structure (which gates act where, not which single-qubit
+           gate), so they are searched once per structure and kept in a plan
+           cache; requests whose plan exceeds the cost cap are refused;
   admit    a planned request starts as soon as a stream slot is free and the
            plans in flight plus its own workspace fit the HBM budget; requests
            that can never fit are refused;
   execute  each admitted request runs on its own HIP stream (contraction of its
            batches, then sampling); completion is polled with events, results are
-           copied out and the request's workspace is released.
+           copied out and the request's workspace is released.  A sampling
+           request that accepted fewer samples than it asked for contracts
+           further batches (drawn by the request) on its stream and samples them
+           with the next sub-batch indices, until it has its count.
 
 Every request's arithmetic is fixed by its plan (deterministic path search,
 fixed kernels and FP64 slice order), so its result does not depend on what
@@ -23,6 +29,7 @@ import math
 import queue
 import threading
 import time
+from collections import OrderedDict
 from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 
@@ -41,6 +48,8 @@ class Request:
     seed: int = 7
     precision: int = 0        # rqc_precision
     arrival: float = 0.0
+    # more fixed-bit masks for sampling beyond fixed_bits: (start, count) -> list
+    more_fixed_bits: object = None
 
 
 @dataclass
@@ -69,6 +78,11 @@ class _Work:
     stream: object = None
     event: object = None
     out: object = None
+    amps: object = None       # host copy of the requested batches' amplitudes
+    cur_fixed: list = field(default_factory=list)  # batches of the round in flight
+    sub_done: int = 0         # sub-batches of 64 already sampled
+    batches_done: int = 0     # batches contracted so far (all rounds)
+    rounds: int = 0
     samples: object = None
     n_out: int = 0
 
@@ -112,6 +126,11 @@ class Server:
         self._alloc_cb = rqc.ALLOC_FN(_alloc)
         self._free_cb = rqc.FREE_FN(_free)
         self.plan_opts.update(alloc=self._alloc_cb, free=self._free_cb)
+        # structure signature -> (path, sliced legs), least recently used first
+        self.plan_cache: "OrderedDict[str, tuple]" = OrderedDict()
+        self.plan_cache_cap = 256
+        self.plan_cache_lock = threading.Lock()
+        self.max_rounds = 16
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self.free_streams = list(range(n_streams))
         self.planner = ThreadPoolExecutor(max_workers=plan_workers)
@@ -120,7 +139,8 @@ class Server:
         self.running: list = []
         self.lock = threading.Lock()
         self.stop = False
-        self.stats = dict(submitted=0, completed=0, refused=0, errors=0)
+        self.stats = dict(submitted=0, completed=0, refused=0, errors=0, short=0, plan_cache_hits=0,
+                          extra_rounds=0)
         self.loop = threading.Thread(target=self._run, daemon=True)
         self.loop.start()
 
@@ -140,11 +160,47 @@ class Server:
         self.planner.shutdown(wait=True)
 
     # -------------------------------------------------------------- stages
+    @staticmethod
+    def structure_key(req: Request, precision: int) -> str:
+        """The circuit text with the single-qubit gate names erased: two circuits
+        with the same key have the same tensor network legs."""
+        lines = []
+        for line in req.text.splitlines():
+            tok = line.split()
+            if tok and tok[0] in ("sx", "sy", "sw"):
+                tok[0] = "g1"
+            lines.append(" ".join(tok))
+        return hashlib.sha256(("\n".join(lines) + f"|{req.open_qubits}|{precision}").encode()).hexdigest()
+
+    def _plan_for(self, req: Request):
+        """Plan on the cached tree and sliced legs of the request's structure;
+        a miss searches once and keeps the result.  Every plan is created from
+        (path, sliced legs), so a request's plan does not depend on the cache."""
+        rqc = self.rqc
+        c = rqc.load_circuit(req.text)
+        key = self.structure_key(req, req.precision)
+        with self.plan_cache_lock:
+            hit = self.plan_cache.get(key)
+            if hit is not None:
+                self.plan_cache.move_to_end(key)
+                self.stats["plan_cache_hits"] += 1
+        opts = dict(self.plan_opts)
+        if hit is None:
+            searched = rqc.plan_create(c, req.open_qubits, precision=req.precision, dry_run=1,
+                                       **{k: v for k, v in opts.items() if k not in ("alloc", "free")})
+            hit = (rqc.plan_path(searched), rqc.plan_sliced_legs(searched))
+            del searched
+            with self.plan_cache_lock:
+                self.plan_cache[key] = hit
+                while len(self.plan_cache) > self.plan_cache_cap:
+                    self.plan_cache.popitem(last=False)
+        path, legs = hit
+        return rqc.plan_create(c, req.open_qubits, path=path, sliced_legs=legs, precision=req.precision, **opts)
+
     def _plan(self, w: _Work):
         rqc = self.rqc
         try:
-            c = rqc.load_circuit(w.req.text)
-            w.plan = rqc.plan_create(c, w.req.open_qubits, precision=w.req.precision, **self.plan_opts)
+            w.plan = self._plan_for(w.req)
             w.info = rqc.plan_info(w.plan)
             o = len(w.req.open_qubits)
             out_bytes = len(w.req.fixed_bits) * (8 << o) + 8 * w.req.n_samples
@@ -162,36 +218,62 @@ class Server:
             self._finish(w, "error", str(e))
 
     def _launch(self, w: _Work, sid: int):
+        """Contract the round's batches (the request's own on the first round)."""
         rqc, torch = self.rqc, self.torch
         req = w.req
         s = self.streams[sid]
         w.stream = sid
-        w.started = time.perf_counter()
+        if w.rounds == 0:
+            w.started = time.perf_counter()
+            w.cur_fixed = list(req.fixed_bits)
         o = len(req.open_qubits)
         with torch.cuda.stream(s):
-            w.out = torch.empty((len(req.fixed_bits), 1 << o, 2), dtype=torch.float32, device="cuda")
-            rqc.contract_amplitudes(w.plan, req.fixed_bits, w.out, stream=s)
+            if w.out is None:
+                w.out = torch.empty((len(req.fixed_bits), 1 << o, 2), dtype=torch.float32, device="cuda")
+            rqc.contract_amplitudes(w.plan, w.cur_fixed, w.out[:len(w.cur_fixed)], stream=s)
             w.event = torch.cuda.Event()
             w.event.record(s)
 
-    def _complete(self, w: _Work):
+    def _complete(self, w: _Work) -> bool:
+        """Sample the finished round; returns False when another round was launched."""
         rqc, torch = self.rqc, self.torch
         req = w.req
         s = self.streams[w.stream]
         try:
+            o = len(req.open_qubits)
+            if w.rounds == 0:
+                torch.cuda.current_stream().wait_stream(s)
+                a = w.out.cpu().numpy()
+                w.amps = a[..., 0] + 1j * a[..., 1]
             if req.n_samples > 0:
-                samples = torch.zeros(req.n_samples, dtype=torch.int64, device="cuda")
-                n_out, st, _ = rqc.rejection_sample(w.out, req.fixed_bits, req.open_qubits, req.n_qubits,
-                                                    req.n_samples, samples, alpha=req.alpha, F_norm=1.0,
-                                                    seed=req.seed, stream=s)
-                w.samples = samples.cpu().numpy()[:n_out]
-                w.n_out = n_out
-            torch.cuda.current_stream().wait_stream(s)
-            a = w.out.cpu().numpy()
-            amps = a[..., 0] + 1j * a[..., 1]
-            self._finish(w, "ok", amps=amps)
+                need = req.n_samples - w.n_out
+                with torch.cuda.stream(s):
+                    buf = torch.empty(need, dtype=torch.int64, device="cuda")
+                    n_out, st, _ = rqc.rejection_sample(w.out[:len(w.cur_fixed)], w.cur_fixed, req.open_qubits,
+                                                        req.n_qubits, need, buf, alpha=req.alpha, F_norm=1.0,
+                                                        seed=req.seed, batch_index_base=w.sub_done, stream=s)
+                got = buf.cpu().numpy()[:n_out]
+                w.samples = got if w.samples is None else np.concatenate([w.samples, got])
+                w.n_out += n_out
+                w.sub_done += len(w.cur_fixed) << (o - 6)
+                w.batches_done += len(w.cur_fixed)
+                if w.n_out < req.n_samples and req.more_fixed_bits is not None and w.rounds < self.max_rounds:
+                    # expected yield about 1/alpha sample per sub-batch; at most
+                    # as many batches as the request's own buffer holds
+                    want = math.ceil(req.alpha * (req.n_samples - w.n_out) * 1.25 / (1 << (o - 6)))
+                    k = max(1, min(len(req.fixed_bits), want))
+                    w.cur_fixed = list(req.more_fixed_bits(w.batches_done, k))
+                    w.rounds += 1
+                    with self.lock:
+                        self.stats["extra_rounds"] += 1
+                    self._launch(w, w.stream)
+                    return False
+            status = "ok" if w.n_out >= req.n_samples else "short"
+            self._finish(w, status, amps=w.amps,
+                         msg="" if status == "ok" else f"{w.n_out} of {req.n_samples} samples")
         except Exception as e:
             self._finish(w, "error", str(e))
+        return True
 
     def _finish(self, w: _Work, status: str, msg: str = "", amps=None):
         now = time.perf_counter()
@@ -200,7 +282,7 @@ class Server:
                    flops=w.info.get("flops_per_batch", 0.0) * len(w.req.fixed_bits), footprint=w.footprint,
                    message=msg)
         with self.lock:
-            key = {"ok": "completed", "refused": "refused", "error": "errors"}[status]
+            key = {"ok": "completed", "refused": "refused", "error": "errors", "short": "short"}[status]
             self.stats[key] += 1
         w.plan = None
         w.out = None
@@ -236,20 +318,36 @@ class Server:
             # completions
             done = [w for w in self.running if w.event.query()]
             for w in done:
+                progressed = True
+                if not self._complete(w):
+                    continue  # another round is in flight on the same stream
                 self.running.remove(w)
-                self._complete(w)
                 self.in_use -= w.footprint
                 self.free_streams.append(w.stream)
-                progressed = True
             if not progressed:
                 time.sleep(0.0002)
 
 
+class _MoreFixedBits:
+    """Further seeded fixed-bit masks of a synthetic request (batch index i
+    draws from seed base + i)."""
+
+    def __init__(self, n_qubits, open_qubits, base):
+        self.n, self.open_q, self.base = n_qubits, list(open_qubits), base
+
+    def __call__(self, start, count):
+        import synthetic
+        return synthetic.fixed_bits_batch(self.n, self.open_q, self.base + start, count)
+
+
 def synthetic_requests(n: int, seed: int = 0, shapes=((4, 5), (4, 6), (5, 5), (5, 6)), cycles=(8, 14),
                        log2_amps=(6, 12), sample_frac: float = 0.5, samples=(1000, 4000), bf16_frac: float = 0.5,
-                       rate: float | None = None):
+                       rate: float | None = None, min_log2_for_samples: int = 10):
     """Seeded request mix: grid shape, depth, 2^u amplitudes, optional samples,
-    precision; Poisson arrival offsets when `rate` (requests/s) is given."""
+    precision; Poisson arrival offsets when `rate` (requests/s) is given.
+    Sampling requests get about alpha = 2 sub-batches of 64 per sample, in
+    batches of at least 2^min_log2_for_samples amplitudes, and draw more
+    masks (seeded) if that does not yield their count."""
     import synthetic
     rng = np.random.default_rng(seed)
     out = []
@@ -262,14 +360,17 @@ def synthetic_requests(n: int, seed: int = 0, shapes=((4, 5), (4, 6), (5, 5), (5
         u = min(u, nq)
         open_q = list(range(nq - u, nq))
         text = synthetic.circuit_text(r, c, m, 10_000 + rid)
-        # sampling requests use batches of at least 2^10 amplitudes (16 sub-batches)
-        ns = int(rng.integers(samples[0], samples[1] + 1)) if rng.random() < sample_frac and u >= 10 else 0
+        ns = int(rng.integers(samples[0], samples[1] + 1)) if rng.random() < sample_frac else 0
+        if ns:
+            u = max(u, min(min_log2_for_samples, nq))
+            open_q = list(range(nq - u, nq))
         n_batches = 1 if ns == 0 else max(1, math.ceil(2.0 * ns / (1 << (u - 6))))
         fixed = synthetic.fixed_bits_batch(nq, open_q, 20_000 + 1000 * rid, n_batches)
         prec = 1 if rng.random() < bf16_frac else 0
         if rate:
             t += float(rng.exponential(1.0 / rate))
-        out.append((t, Request(rid, text, nq, open_q, fixed, n_samples=ns, precision=prec)))
+        more = _MoreFixedBits(nq, open_q, 20_000 + 1000 * rid) if ns else None
+        out.append((t, Request(rid, text, nq, open_q, fixed, n_samples=ns, precision=prec, more_fixed_bits=more)))
     return out
 
 

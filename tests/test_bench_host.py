@@ -13,35 +13,61 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _prof(gemm_s, stream_s):
-    return {
-        "gemm": {"seconds": gemm_s, "flops": 8e12, "bytes": 4e9, "launches": 4},
-        "stream": {"seconds": stream_s, "flops": 1e12, "bytes": 4e12, "launches": 8},
-        "sample": {"seconds": 10.0, "flops": 0.0, "bytes": 0.0, "launches": 1},  # never the dominant class
-    }
+def _rec(cls, seconds, flops, bytes_, exec_flops, kind=0, launches=1, op=0):
+    return {"cls": cls, "op": op, "launches": launches, "seconds": seconds, "flops": flops, "bytes": bytes_,
+            "exec_flops": exec_flops, "exec_kind": kind}
+
+
+def _ops(gemm_s, stream_s, kind=0):
+    g_exec = 8e12 * (6.0 / 8.0 if kind == 0 else 3.0)
+    return [
+        _rec("gemm", gemm_s, 8e12, 4e9, g_exec, kind, launches=4, op=1),
+        # two streaming ops: one HBM-bound, one bound by its matrix-core stages
+        _rec("stream", 0.5 * stream_s, 0.1e12, 3.9e12, 0.1e12, launches=4, op=2),
+        _rec("stream", 0.5 * stream_s, 0.9e12, 0.1e12, 0.9e12, launches=4, op=3),
+        _rec("sample", 10.0, 0.0, 0.0, 0.0, op=-1),  # never the dominant class
+    ]
 
 
 def test_gemm_roofline_counts_executed_matrix_core_flops():
-    r = bench.kernel_roofline(_prof(1.0, 0.5), True)
+    r = bench.kernel_roofline(_ops(1.0, 0.5))
     # 8e12 flops counted at 8 per complex multiply-add = 1e12 multiply-adds,
     # 6 executed flops each on the FP32 matrix cores (three real products)
     assert r["kernel"] == "gemm" and r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
     assert r["achieved"] == pytest.approx(6.0)
     assert r["peak"] == 157.3 and r["frac"] == pytest.approx(6.0 / 157.3)
+    assert r["binding_frac"] == pytest.approx(6.0 / 157.3)
     assert r["avg_launch_us"] == pytest.approx(0.25e6)
     assert r["bytes_per_launch"] == pytest.approx(1e9)
-    r = bench.kernel_roofline(_prof(1.0, 0.5), False)
+    r = bench.kernel_roofline(_ops(1.0, 0.5, kind=1))
     # split precision: three half-precision products per real product
     assert r["achieved"] == pytest.approx(24.0) and r["peak"] == 2516.6
 
 
-def test_stream_roofline_is_hbm_bound_with_matrix_core_side():
-    r = bench.kernel_roofline(_prof(0.5, 1.0), True)
-    assert r["kernel"] == "stream" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+def test_stream_roofline_binds_per_op():
+    r = bench.kernel_roofline(_ops(0.5, 1.0))
+    assert r["kernel"] == "stream"
+    # per op: 3.9e12 B / 8 TB/s = 0.4875 s; the second op: max(0.9e12 flop /
+    # 157.3 TFLOP/s, 0.1e12 B / 8 TB/s) = 12.5 ms
+    tmin = 3.9e12 / 8e12 + max(0.9e12 / 157.3e12, 0.1e12 / 8e12)
+    assert r["binding_frac"] == pytest.approx(tmin / 1.0)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
     assert r["achieved"] == pytest.approx(4000.0) and r["frac"] == pytest.approx(0.5)
     assert r["mfma_side"]["achieved"] == pytest.approx(1.0)
     assert r["launches"] == 8 and r["bytes_per_launch"] == pytest.approx(5e11)
     assert r["traffic"] is None  # no plan named
+    # the class whose minimum time is mostly matrix-core time reports that roof
+    ops = [_rec("stream", 1.0, 1e14, 1e11, 1e14), _rec("gemm", 0.1, 1e9, 1e6, 1e9)]
+    r = bench.kernel_roofline(ops)
+    assert r["bound"] == "mfma" and r["frac"] == pytest.approx(100.0 / 157.3)
+
+
+def test_path_roofline_sums_per_op_minimum_times():
+    ops = _ops(1.0, 0.5)
+    r = bench.path_roofline(ops, 2.0)
+    t = max(8e12 / 157.3e12, 4e9 / 8e12) + max(0.1e12 / 157.3e12, 3.9e12 / 8e12) + \
+        max(0.9e12 / 157.3e12, 0.1e12 / 8e12)
+    assert r["tmin_seconds"] == pytest.approx(t) and r["frac"] == pytest.approx(t / 2.0)
 
 
 def test_more_than_one_gpu_is_refused():

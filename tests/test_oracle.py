@@ -266,3 +266,132 @@ def test_eps_estimate_unbiased():
     full = float(np.maximum(0, pj - 1.1 / nb).sum())
     est = stats.eps_estimate(pj[:2048], nb, 1.1)
     assert abs(est - full) < 0.3 * full + 1e-4
+
+
+# ---------------------------------------------------------------- Eq. (9) bound: pins from its derivation
+
+def _bures_chain_solution(f, d):
+    """The tightest f' that the Bures triangle step of Sec. II.B allows:
+    sqrt(1 - sqrt(f')) <= sqrt(1 - sqrt(f)) + sqrt(d), solved for f'."""
+    s = 1.0 - (math.sqrt(1.0 - math.sqrt(f)) + math.sqrt(d)) ** 2
+    return max(0.0, s) ** 2
+
+
+def test_fidelity_bound_limits():
+    """At the validity edge d = f/16 the factor 1 - 4 sqrt(d/f) is exactly 0,
+    and as d -> 0 the bound returns to f.  A bound without the square root
+    (0.75 f at the edge) or without the factor 4 (0.75 f as well) fails."""
+    for f in (0.002, 0.011, 0.3, 0.9):
+        edge = f / 16.0
+        b = stats.fidelity_bound(f, edge * (1.0 - 1e-12))
+        assert b is not None and 0.0 <= b < 1e-5 * f
+        assert stats.fidelity_bound(f, edge) is None
+        assert abs(stats.fidelity_bound(f, 1e-40) - f) <= 1e-15 * f
+        # half-way in sqrt(d/f): 4 sqrt(d/f) = 1/2 exactly at d = f/64
+        assert abs(stats.fidelity_bound(f, f / 64.0) - 0.5 * f) <= 1e-14 * f
+
+
+def test_fidelity_bound_below_bures_chain():
+    """Eq. (9) relaxes the exact solution of the triangle inequality (6)-(8):
+    it never exceeds it, and the two agree to first order in sqrt(d) for
+    small f (both are f - 4 sqrt(f d) + O(d))."""
+    for f in (0.001, 0.01, 0.02, 0.2, 0.7):
+        for r in np.linspace(1e-6, 1.0 - 1e-6, 200):
+            d = r * f / 16.0
+            b = stats.fidelity_bound(f, d)
+            assert b is not None and b <= _bures_chain_solution(f, d) + 1e-15
+    f, d = 1e-3, 1e-12
+    slope_bound = (f - stats.fidelity_bound(f, d)) / math.sqrt(d)
+    slope_chain = (f - _bures_chain_solution(f, d)) / math.sqrt(d)
+    assert abs(slope_bound / slope_chain * math.sqrt(1.0 - math.sqrt(f)) - 1.0) < 1e-3
+
+
+def test_fidelity_bound_holds_for_sampled_law():
+    """Monte Carlo over random states: psi' with |<psi|psi'>|^2 = f, sampled by
+    the Sec. II.A law p~ (alpha chosen to make d small): the classical fidelity
+    between |psi|^2 and p~ is at least the bound of Eq. (9) with d = D(p, p~)."""
+    rng = np.random.default_rng(11)
+    n = 10
+    for trial in range(20):
+        f = float(rng.uniform(0.05, 0.95))
+        psi = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+        psi /= np.linalg.norm(psi)
+        perp = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+        perp -= np.vdot(psi, perp) * psi
+        perp /= np.linalg.norm(perp)
+        psi2 = math.sqrt(f) * psi + math.sqrt(1 - f) * perp
+        assert abs(abs(np.vdot(psi, psi2)) ** 2 - f) < 1e-12
+        p = (np.abs(psi2) ** 2).reshape(16, 64)
+        for alpha in (1.05, 1.2, 2.0):
+            pt, eps, _ = stats.sampler_law(p, alpha)
+            d = stats.tv_distance(p.reshape(-1), pt.reshape(-1))
+            assert d <= eps + 1e-15
+            b = stats.fidelity_bound(f, d)
+            if b is None:
+                continue
+            q = np.abs(psi) ** 2
+            f_cl = float(np.sqrt(q * pt.reshape(-1)).sum() ** 2)
+            assert f_cl >= b
+
+
+# ---------------------------------------------------------------- batches mode: eps_J and the output law
+
+def test_batches_mode_eps_equals_closed_form_with_f_norm():
+    """Visiting all N_B batches once, eps_J equals the closed-form eps of
+    Sec. II.A, also when the amplitudes are not normalised (F_norm != 1):
+    the oracle must divide the capped excess by F_norm."""
+    a, p = _full_p(seed=4)
+    for scale in (1.0, 0.37, 2.9):
+        amps = (a * np.float32(math.sqrt(scale))).astype(np.complex64).reshape(64, 64)
+        pr = sampler.probabilities(amps)
+        f_norm = float(pr.sum())
+        for alpha in (1.1, 1.2, 2.0):
+            _, st = sampler.sample_batches(amps, 6, 64, alpha, f_norm, 9, 0, 0)
+            _, eps, _ = stats.sampler_law(pr / f_norm, alpha)
+            assert abs(st["eps_j"] - eps) <= 1e-12
+    # capping is exercised at alpha = 1.1 on this 12-qubit vector
+    _, eps11, _ = stats.sampler_law(sampler.probabilities(a.reshape(64, 64)), 1.1)
+    assert eps11 > 1e-3
+
+
+def test_batches_mode_output_law_chi2():
+    """Batches mode visits each batch once with its own Philox stream: over
+    many visits of 16 batches of N_A = 4, the accepted (j, i) counts follow
+    t_j p_ij / p_j, i.e. the closed-form law p~ of Sec. II.A (chi-squared,
+    63 degrees of freedom), with heavy batches capped (alpha = 1.2)."""
+    rng = np.random.default_rng(6)
+    P = rng.exponential(size=(16, 4)) * np.linspace(0.3, 2.5, 16)[:, None]
+    P /= P.sum()
+    amps = np.sqrt(P).astype(np.complex64)
+    pr = sampler.probabilities(amps)
+    f_norm = float(pr.sum())
+    reps = 6000
+    tiled = np.tile(amps, (reps, 1))
+    out, st = sampler.sample_batches(tiled, 2, 16, 1.2, f_norm, 21, 12345, 10 ** 9)
+    pt, eps, acc_rate = stats.sampler_law(pr / f_norm, 1.2)
+    assert eps > 0.05
+    cnt = np.zeros(64)
+    for j, i in out:
+        cnt[(j % 16) * 4 + i] += 1
+    n = cnt.sum()
+    expc = pt.reshape(-1) * n
+    chi = float(((cnt - expc) ** 2 / expc).sum())
+    assert chi < 63 + 6 * math.sqrt(2 * 63)
+    # acceptance per visited batch: mean of t_j = (1 - eps) / alpha * 16 / N_B (N_B = 16 here)
+    rate = st["accepted"] / tiled.shape[0]
+    sd = math.sqrt(acc_rate * (1 - acc_rate) / tiled.shape[0])
+    assert abs(rate - acc_rate) < 5 * sd
+
+
+def test_package_estimates_agree_with_oracle():
+    """The package's host estimates (used in the benchmark report) against the
+    oracle's, which the pins above fix."""
+    from paper_2112_15083_amd import estimates
+    for f, d in ((0.011, 5e-6), (0.3, 0.001), (2.0 ** -18, 4.3e-12), (0.01, 0.01 / 16)):
+        a, b = estimates.fidelity_bound(f, d), stats.fidelity_bound(f, d)
+        assert (a is None and b is None) or abs(a - b) <= 1e-15 * f
+    for alpha in (1.1, 1.5, 2.0):
+        assert abs(estimates.expected_eps(64, alpha) - stats.expected_eps(64, alpha)) <= 1e-15
+    rng = np.random.default_rng(2)
+    pj = rng.gamma(64, 1 / 64, size=500) / 4096
+    assert abs(estimates.eps_estimate(pj, 4096, 1.1) - stats.eps_estimate(pj, 4096, 1.1)) <= 1e-12

@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 import synthetic
 from oracle import circuit as oc
@@ -84,3 +85,30 @@ def test_full_alg1_and_xeb_tracks_fidelity():
     s = rng.choice(q.size, size=200_000, p=q / q.sum())
     x = stats.xeb(CIRC.n, p[s])
     assert abs(x - xeb_exact) < 4 * math.sqrt(2.0 / s.size) * 3
+
+
+@pytest.mark.parametrize("rows,cols,cycles,seed,near", [(3, 4, 8, 0, True), (4, 4, 10, 1, True), (3, 4, 8, 2, False)])
+def test_lightcone_norms_equal_full_state_vector_norms(rows, cols, cycles, seed, near):
+    """Two routes to R: projected full state vectors, and the light cone of S
+    split into qubit-disjoint parts.  Near-input S (cones of at most four
+    vertices) and a deeper Alg. 2 selection."""
+    text = synthetic.circuit_text(rows, cols, cycles, seed)
+    c = oc.parse(text)
+    lc = partial.LightCones(c)
+    n = c.n
+    internal = [v for v, gi, q in c.variables() if gi >= 0]
+    if near:
+        cand = [v for v in internal if len(lc.vertices([v])) <= 4]
+        S = []
+        for v in cand:
+            if all(v not in lc.vertices([u]) and u not in lc.vertices([v]) for u in S):
+                S.append(v)
+            if len(S) == 6:
+                break
+    else:
+        S = partial.sliced_vertex_select(c, internal[n:n + 40], 5)
+    assert partial.is_antichain(c, S)
+    a = partial.norms_R(text, S)
+    b = partial.norms_R_lightcone(text, S)
+    assert abs(a.sum() - 1.0) < 1e-12 and abs(b.sum() - 1.0) < 1e-12
+    assert np.abs(a - b).max() <= 1e-13
