@@ -18,6 +18,16 @@ LIB_PATH = os.path.join(_HERE, "librqc.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"librqc.so is not built ({LIB_PATH}); run python -m paper_2112_15083_amd.build")
 
+# One HIP runtime per process: PyTorch ships its own libamdhip64 (soname
+# libamdhip64.so.7).  Loaded first, it satisfies librqc's dependency of that
+# soname, so the streams and device pointers torch hands over belong to the
+# runtime the library calls.  Loaded after librqc, it would come in as a second
+# runtime beside the system one, and one of the two would find no device.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the library itself does not need torch
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, EPARSE, EPLAN, ENOMEM, EDEVICE, ESHORT = 0, -1, -2, -3, -4, -5, -6

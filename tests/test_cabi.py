@@ -35,6 +35,20 @@ def test_every_declared_symbol_is_exported(rqc):
     assert set(syms) == set(rqc.EXPORTS)
 
 
+def test_one_hip_runtime_whatever_the_import_order(rqc):
+    """The binding loads torch's HIP runtime before the library, so importing the
+    binding first and torch afterwards still maps a single libamdhip64 (two
+    runtimes in one process do not share devices, streams or pointers)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2112_15083_amd import rqc\nimport torch\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
+
+
 def test_parse_errors_are_reported(rqc):
     with pytest.raises(rqc.RqcError) as e:
         rqc.load_circuit("qubits 2\nsx 0 5\n")
