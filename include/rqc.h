@@ -145,6 +145,11 @@ typedef struct {
        of going through HBM.  Results agree with the unfused plan to FP32
        rounding (the second contraction may add its index in another order). */
     int32_t no_stream_fusion;
+    /* 1 = run every streaming step on the vector-ALU kernels instead of the
+       matrix-core forms (and unfused): an ablation, and the route that checks
+       those kernels against the oracle.  Slower; results agree to FP32
+       rounding. */
+    int32_t no_matrix_core_streams;
 } rqc_plan_opts;
 
 typedef struct {
@@ -176,6 +181,10 @@ typedef struct {
     double est_seconds;        /* the planner's estimate of one batch's GPU time
                                   (what it minimises over candidate trees) */
     int32_t n_fused;           /* streaming pairs run fused (see no_stream_fusion) */
+    /* streaming launches per slice group by kernel: [0] fused pair, [1]
+       matrix-core tile, [2] matrix-core long contraction, [3] vector long
+       contraction, [4] vector LDS tile, [5] vector generic; [6], [7] unused */
+    int32_t stream_kernels[8];
 } rqc_plan_info_t;
 
 typedef struct {

@@ -193,6 +193,12 @@ struct StreamOp {
     BitMap m[SM_COUNT];
 };
 
+// The kernel a streaming op runs on (launch_stream dispatches on this, and the
+// plan report counts it): fused pair, matrix-core tile, matrix-core long
+// contraction, then the vector-ALU forms: long contraction, LDS tile, generic.
+enum StreamKernel { SK_MX2 = 0, SK_MX, SK_LK, SK_KY, SK_TILE, SK_GEN, SK_COUNT };
+int stream_kernel(const StreamOp &op);
+
 struct PermuteOp {  // dst[pi(x)] = src[x]
     Buf src, dst;
     int r;

@@ -90,55 +90,6 @@ void launch_small_trees(const SmallStep *d_steps, const SmallTree *d_trees, int 
 }
 
 // ------------------------------------------------------------------ streaming contraction
-// Register-blocked form: a thread owns one r (the C index without B's new
-// legs), loads its 2^kc operand values of A once and writes all 2^nf outputs
-// that share them, so A is read from HBM once.  Threads of a block take 256
-// consecutive r; the low 8 bits of r map through per-thread offsets, the high
-// bits through one uniform map per chunk.
-template <int KMAX, int FMAX>
-__global__ void __launch_bounds__(256) k_stream_rb(const float2 *__restrict__ A, const float2 *__restrict__ B,
-                                                   float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
-                                                   int kc, int nf) {
-    __shared__ int64_t tyA[KMAX], tyB[KMAX], tfB[FMAX], tfC[FMAX];
-    const int tid = threadIdx.x;
-    const int nK = 1 << kc, nF = 1 << nf;
-    if (tid < nK) {
-        tyA[tid] = map_apply(maps[SM_YA], tid);
-        tyB[tid] = map_apply(maps[SM_YB], tid);
-    }
-    if (tid < nF) {
-        tfB[tid] = map_apply(maps[SM_FB], tid);
-        tfC[tid] = map_apply(maps[SM_FC], tid);
-    }
-    __syncthreads();
-    const int lo_bits = nr < 8 ? nr : 8;
-    if (tid >= (1 << lo_bits)) return;
-    const int64_t a_lo = map_apply(maps[SM_RA], tid), b_lo = map_apply(maps[SM_RB], tid),
-                  c_lo = map_apply(maps[SM_RC], tid);
-    const int64_t n_chunks = (int64_t)1 << (nr - lo_bits);
-    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        const int64_t r0 = ch << lo_bits;
-        const int64_t ab = map_apply(maps[SM_RA], r0) + a_lo;
-        const int64_t bb = map_apply(maps[SM_RB], r0) + b_lo;
-        const int64_t cb = map_apply(maps[SM_RC], r0) + c_lo;
-        float2 a[KMAX];
-#pragma unroll
-        for (int y = 0; y < KMAX; y++)
-            if (y < nK) a[y] = A[ab + tyA[y]];
-#pragma unroll
-        for (int f = 0; f < FMAX; f++) {
-            if (f < nF) {
-                float2 acc = make_float2(0.f, 0.f);
-                const float2 *bp = B + bb + tfB[f];
-#pragma unroll
-                for (int y = 0; y < KMAX; y++)
-                    if (y < nK) cmac(acc, a[y], bp[tyB[y]]);
-                C[cb + tfC[f]] = acc;
-            }
-        }
-    }
-}
-
 // General form for long contracted or new-leg dimensions: one output per
 // thread and iteration, contracted offsets tabulated in LDS (low 10 bits) and
 // mapped per high part.
@@ -783,7 +734,8 @@ void launch_stream_mx(const StreamOp &op, const BitMap *d_maps, const float2 *a,
 
 void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
                    float2 *w, const float2 *b2, hipStream_t s) {
-    if (op.mx2) {
+    const int kind = stream_kernel(op);
+    if (kind == SK_MX2) {
         if (op.tile_l != 6 || (op.kc != 4 && op.kc != 5) || op.nf != 5 || op.kc2 != 4 || op.nf2 != 4 || op.nr < 8 ||
             op.nr > 36 || !b2)
             fail(RQC_EPLAN, "fused streaming pair exceeds the kernel's limits");
@@ -797,7 +749,7 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
         else go(k_stream_mx2<5, 4>);
         return;
     }
-    if (op.mx) {
+    if (kind == SK_MX) {
         if (op.tile_l < 6 || op.tile_l > 8 || op.tile_l + op.kc > 11 || op.tile_l + op.nf > (op.nf == 6 ? 12 : 11) ||
             op.kc > 5 || op.nf > 6 || op.nr < op.tile_l)
             fail(RQC_EPLAN, "matrix-core streaming tile exceeds the kernel's limits");
@@ -811,7 +763,7 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
         }
         return;
     }
-    if (op.lk) {
+    if (kind == SK_LK) {
         if (op.kc < 6 || op.nf > 5 || op.nr < 6 || op.lk_split < 0 || op.lk_split > op.kc - 5 || (op.lk_split && !w))
             fail(RQC_EPLAN, "long streaming contraction exceeds the kernel's limits");
         const int64_t blocks = (int64_t)1 << (op.nr - 6 + op.lk_split);
@@ -830,13 +782,13 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
         }
         return;
     }
-    if (op.tile_l < 0 && op.kc >= 6 && op.nf <= 4) {
+    if (kind == SK_KY) {
         const int64_t waves = (int64_t)1 << op.nr;
         const dim3 g((unsigned)((waves + 3) / 4)), t(256);
         hipLaunchKernelGGL((k_stream_ky<16>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
         return;
     }
-    if (op.tile_l >= 0) {
+    if (kind == SK_TILE) {
         if (op.tile_l > 8 || op.tile_l + op.kc > 11 || op.tile_l + op.nf > 11 || op.kc > 5)
             fail(RQC_EPLAN, "streaming tile exceeds the kernel's limits");
         const int64_t tiles = (int64_t)1 << (op.nr - op.tile_l);
@@ -849,19 +801,10 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
             hipLaunchKernelGGL((k_stream_tile<32, 0>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf, op.tile_l);
         return;
     }
-    const int lo = op.nr < 8 ? op.nr : 8;
-    const int64_t chunks = (int64_t)1 << (op.nr - lo);
-    const unsigned blocks = (unsigned)std::min<int64_t>(chunks, 256 * 16);
-    const dim3 g(blocks), t(256);
-    if (op.kc <= 2 && op.nf <= 2) hipLaunchKernelGGL((k_stream_rb<4, 4>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
-    else if (op.kc <= 4 && op.nf <= 2) hipLaunchKernelGGL((k_stream_rb<16, 4>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
-    else if (op.kc <= 2 && op.nf <= 4) hipLaunchKernelGGL((k_stream_rb<4, 16>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
-    else if (op.kc <= 4 && op.nf <= 4) hipLaunchKernelGGL((k_stream_rb<16, 16>), g, t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
-    else {
-        const int64_t n = (int64_t)1 << op.rc;
-        const unsigned gb = (unsigned)std::min<int64_t>((n + 255) / 256, 256 * 64);
-        hipLaunchKernelGGL(k_stream_gen, dim3(gb), t, 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
-    }
+    // SK_GEN
+    const int64_t n = (int64_t)1 << op.rc;
+    const unsigned gb = (unsigned)std::min<int64_t>((n + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_stream_gen, dim3(gb), dim3(256), 0, s, a, b, c, d_maps, op.nr, op.kc, op.nf);
 }
 
 // ------------------------------------------------------------------ permute

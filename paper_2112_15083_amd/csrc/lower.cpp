@@ -102,10 +102,12 @@ struct Lowerer {
     // fused streaming pairs: deferred[t] = step t runs inside its parent's op
     bool fuse = true;
     std::vector<char> deferred;
+    // matrix-core streaming forms allowed (off: vector-ALU kernels only)
+    bool mx_streams = true;
 
     Lowerer(const Tree &t, const std::vector<Legs> &l, Program &p, const std::vector<char> &leaf_dep, bool cache_,
-            bool fuse_)
-        : tree(t), legs(l), prog(p), cache(cache_), fuse(fuse_) {
+            bool fuse_, bool mx_)
+        : tree(t), legs(l), prog(p), cache(cache_), fuse(fuse_ && mx_), mx_streams(mx_) {
         nt = t.n_leaves + (int)t.steps.size();
         layout.resize(nt);
         where.resize(nt);
@@ -673,7 +675,7 @@ struct Lowerer {
         // At most two batch legs fit a tile (they are its top row bits); further
         // ones are passed over for the next non-batch legs, which costs some
         // contiguity of the tile but keeps the step on the matrix cores.
-        if (L >= 6 && op.kc <= 5 && op.nf <= 6) {
+        if (mx_streams && L >= 6 && op.kc <= 5 && op.nf <= 6) {
             std::vector<int> tile;
             int nbt = 0;
             for (size_t i = 0; i < rest.size() && (int)tile.size() < L; i++)
@@ -696,7 +698,7 @@ struct Lowerer {
         // Long contraction on matrix cores: 64 rows per workgroup from six
         // non-batch kept legs (lowest A positions first), 32-wide chunks of the
         // contracted index from its five legs with the lowest A positions.
-        if (L == 0 && op.kc >= 6 && op.nf <= 5) {
+        if (mx_streams && L == 0 && op.kc >= 6 && op.nf <= 5) {
             std::vector<int> nbr;
             for (int j : rest)
                 if (!is_batch(j)) nbr.push_back(j);
@@ -1100,12 +1102,22 @@ struct Lowerer {
     }
 };
 
+int stream_kernel(const StreamOp &op) {
+    if (op.mx2) return SK_MX2;
+    if (op.mx) return SK_MX;
+    if (op.lk) return SK_LK;
+    if (op.tile_l < 0 && op.kc >= 6 && op.nf <= 4) return SK_KY;
+    if (op.tile_l >= 0) return SK_TILE;
+    return SK_GEN;
+}
+
 // Lower the tree.  leaf_offsets: element offset of each projected leaf in the
 // leaf buffer.  Returns the root layout through `root_layout`.
 Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
-                   const std::vector<char> &leaf_dep, bool cache, bool fuse, std::vector<int> &root_layout) {
+                   const std::vector<char> &leaf_dep, bool cache, bool fuse, bool mx_streams,
+                   std::vector<int> &root_layout) {
     Program prog;
-    Lowerer L(tree, legs, prog, leaf_dep, cache, fuse);
+    Lowerer L(tree, legs, prog, leaf_dep, cache, fuse, mx_streams);
     L.run(leaf_offsets);
     root_layout = L.layout[tree.root()];
     return prog;

@@ -9,7 +9,8 @@
 namespace rqc {
 
 Program lower_tree(const Tree &tree, const std::vector<Legs> &legs, const std::vector<int> &leaf_offsets,
-                   const std::vector<char> &leaf_dep, bool cache, bool fuse, std::vector<int> &root_layout);
+                   const std::vector<char> &leaf_dep, bool cache, bool fuse, bool mx_streams,
+                   std::vector<int> &root_layout);
 
 void sort_leaf(Leaf &L) {
     std::vector<int> order(L.legs.size());
@@ -462,7 +463,7 @@ void plan_finish(PlanCore &p) {
         for (int v : sp.leaves[i].legs)
             if (is_fixed[v]) leaf_dep[i] = 1;
     p.prog = lower_tree(p.tree, legs, leaf_off, leaf_dep, p.opts.global_cache != 0, p.opts.no_stream_fusion == 0,
-                        root_layout);
+                        p.opts.no_matrix_core_streams == 0, root_layout);
     Program &pg = p.prog;
     pg.leafbuf_elems = buf_off;
     if ((size_t)pg.small_lds_elems * 8 > 65536) fail(RQC_EPLAN, "fused subtree needs more than 64 KiB of LDS");
@@ -509,7 +510,11 @@ void plan_finish(PlanCore &p) {
     }
     I.est_seconds = estimate_seconds(p);
     I.n_fused = 0;
-    for (const StreamOp &so : pg.streams) I.n_fused += so.mx2;
+    for (int k = 0; k < SK_COUNT; k++) I.stream_kernels[k] = 0;
+    for (const StreamOp &so : pg.streams) {
+        I.n_fused += so.mx2;
+        I.stream_kernels[stream_kernel(so)]++;
+    }
 }
 
 } // namespace rqc

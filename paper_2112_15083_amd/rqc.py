@@ -35,6 +35,9 @@ C64, BF16X3, FP16X3 = 0, 1, 2
 K_LEAF, K_SMALL, K_STREAM, K_PERMUTE, K_GEMM, K_ACCUM, K_FINAL, K_SAMPLE = range(8)
 K_NAMES = ["leaf_select", "small_trees", "stream", "permute", "gemm", "accumulate", "finalize", "sample"]
 
+# rqc_plan_info_t.stream_kernels entries
+STREAM_KERNELS = ["mx2", "mx", "lk", "ky", "tile", "gen"]
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -48,7 +51,7 @@ class PlanOpts(ctypes.Structure):
                 ("path_seed", ctypes.c_uint64), ("profile", ctypes.c_int32), ("dry_run", ctypes.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
                 ("global_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("no_stream_fusion", ctypes.c_int32)]
+                ("no_stream_fusion", ctypes.c_int32), ("no_matrix_core_streams", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -61,10 +64,13 @@ class PlanInfo(ctypes.Structure):
                 ("n_launches", ctypes.c_int32), ("n_groups", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
                 ("cache_bytes", ctypes.c_int64), ("flops_cached", ctypes.c_double),
-                ("est_seconds", ctypes.c_double), ("n_fused", ctypes.c_int32)]
+                ("est_seconds", ctypes.c_double), ("n_fused", ctypes.c_int32),
+                ("stream_kernels", ctypes.c_int32 * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["stream_kernels"] = dict(zip(STREAM_KERNELS, list(self.stream_kernels)))
+        return d
 
 
 class SampleStats(ctypes.Structure):
@@ -189,7 +195,7 @@ class Circuit:
         self.handle = handle
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.rqc_circuit_destroy(self.handle)
             self.handle = None
 
@@ -200,7 +206,7 @@ class Plan:
         self.open_qubits = list(open_qubits)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.rqc_plan_destroy(self.handle)
             self.handle = None
 

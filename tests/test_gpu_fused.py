@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import synthetic
-from gpu_common import rel_l2
+from gpu_common import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +56,9 @@ def test_fused_pairs_match_unfused_and_oracle(rqc, name, n_fused):
         torch.cuda.synchronize()
         a = o.cpu().numpy()[0]
         outs.append(a[:, 0].astype(np.float64) + 1j * a[:, 1])
-    assert rel_l2(outs[1], outs[0]) <= 5e-6
+    assert_close(outs[1], outs[0], 5e-6, "fused vs unfused")
     for a in outs:
-        assert rel_l2(a, ref) <= 1e-5
+        assert_close(a, ref, 1e-5)
     # a second batch with other fixed bits through the same plans
     fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + 5)]
     got = []
@@ -68,4 +68,4 @@ def test_fused_pairs_match_unfused_and_oracle(rqc, name, n_fused):
         torch.cuda.synchronize()
         a = o.cpu().numpy()[0]
         got.append(a[:, 0].astype(np.float64) + 1j * a[:, 1])
-    assert rel_l2(got[1], got[0]) <= 5e-6
+    assert_close(got[1], got[0], 5e-6, "fused vs unfused")

@@ -16,7 +16,7 @@ from oracle import circuit as oc
 from oracle import partial as opart
 from oracle import sv as osv
 
-from gpu_common import rel_l2
+from gpu_common import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -80,7 +80,7 @@ def test_partial_slicing_matches_oracle(rqc, rows, cols, cycles, seed, n_sliced,
     assert abs(Fo - R_ref[X].sum()) <= 1e-12
     for b in range(2):
         ref = osv.batch_amplitudes(px, fixed[b], open_q) / math.sqrt(Fo)
-        assert rel_l2(got[b], ref) <= 1e-5
+        assert_close(got[b], ref, 1e-5)
 
 
 def test_partial_count_reading(rqc):

@@ -7,7 +7,7 @@ import pytest
 import synthetic
 from oracle import sampler as osamp
 
-from gpu_common import circuit, oracle_batches, rel_l2
+from gpu_common import assert_close, circuit, oracle_batches, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -45,6 +45,8 @@ def test_precision_modes_against_oracle(rqc, rows, cols, cycles, seed, n_sliced)
         a = a[..., 0] + 1j * a[..., 1]
         amps[mode] = a
         errs[mode] = max(rel_l2(a[b], ref[b]) for b in range(2))
+        for b in range(2):
+            assert_close(a[b], ref[b], BARS[mode], f"{mode} batch {b}")
         assert errs[mode] <= BARS[mode], (mode, errs)
     # the split modes really take another arithmetic route
     assert not np.array_equal(amps["C64"], amps["BF16X3"])
