@@ -345,6 +345,33 @@ rqc_status rqc_rejection_sample(const void *amps, const uint64_t *fixed_bits, in
                                 void *hip_stream);
 
 /*
+ * rqc_rejection_sample for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: serving loops and harnesses that forbid it).
+ * Same arguments, results and errors as rqc_rejection_sample, bit for bit; the
+ * difference is where the per-call scratch lives (per sub-batch results, the
+ * fixed bits and open qubits copied to the device, the compaction counters):
+ * in a fixed array of RQC_SAMPLE_STATIC_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends.  The call allocates nothing.
+ * A call needs 16 * items + 8 * n_batches + 4 * n_open bytes plus 1 KiB of
+ * alignment and counters (items = n_batches * 2^(n_open - log2_NA), or
+ * pick_steps); a call needing more returns RQC_EINVAL before any GPU work
+ * (about 5.2e5 sub-batches fit).  Every call on a device shares that device's
+ * array, which keeps the last call's contents (each call writes every word it
+ * reads before reading it, so nothing has to start at zero).  Calls that
+ * overlapped on one device would race on the array: the library serialises
+ * them with a per-device lock held until the call's GPU work has finished (the
+ * call synchronises hip_stream before returning), so only calls from other
+ * processes, which hold their own arrays, run beside it.
+ */
+#define RQC_SAMPLE_STATIC_SCRATCH_BYTES (8u << 20)
+rqc_status rqc_rejection_sample_static(const void *amps, const uint64_t *fixed_bits, int64_t n_batches,
+                                       const int32_t *open_qubits, int32_t n_open, int32_t log2_NA,
+                                       int32_t n_qubits, double alpha, double F_norm, uint64_t seed,
+                                       uint64_t batch_index_base, int64_t pick_steps, int64_t n_samples,
+                                       uint64_t *out_samples, int64_t *n_out, rqc_sample_stats *stats,
+                                       void *hip_stream);
+
+/*
  * Kernel-level primitives (the contraction steps of Sec. I run on these; they
  * are exported for direct use and for testing each kernel variant).
  *

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "host.hpp"
 
 namespace rqc {
@@ -58,7 +60,7 @@ void launch_zero(double2 *acc, int64_t n, hipStream_t s);
 void launch_finalize(const double2 *acc, int64_t n, double scale, float2 *out, double2 *out64,
                      hipStream_t s);
 
-// sampler: `scratch` is device memory of at least sampler_scratch_bytes(items,
+// sampler: `work` is device memory of at least sampler_scratch_bytes(items,
 // batches, n_open) bytes, where items = pick_steps in pick mode, else
 // n_batches * 2^(n_open - log2_na); fixed and open_q are host arrays.  The
 // call synchronises s before returning.
@@ -66,6 +68,12 @@ size_t sampler_scratch_bytes(int64_t n_items, int64_t n_batches, int n_open);
 hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batches, const int32_t *open_q,
                        int n_open, int log2_na, int n_qubits, double alpha, double f_norm, uint64_t seed,
                        uint64_t base, int64_t pick_steps, int64_t n_samples, uint64_t *out,
-                       int64_t *n_out, rqc_sample_stats *stats, void *scratch, hipStream_t s);
+                       int64_t *n_out, rqc_sample_stats *stats, void *work, hipStream_t s);
+
+// The fixed device array of rqc_rejection_sample_static on the current device
+// (its address from hipGetSymbolAddress, looked up once per device) and the
+// lock that serialises the calls using it on that device.
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(void **ptr, std::mutex **call_mu);
 
 } // namespace rqc

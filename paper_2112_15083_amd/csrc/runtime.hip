@@ -766,32 +766,74 @@ rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64
     });
 }
 
+// Argument checks shared by the two sampling entry points; returns the number
+// of sampled items (sub-batches, or steps in pick mode).
+static int64_t check_sample_args(const void *amps, const uint64_t *fixed_bits, int64_t n_batches,
+                                 const int32_t *open_qubits, int32_t n_open, int32_t log2_NA, int32_t n_qubits,
+                                 double alpha, double F_norm, int64_t pick_steps, int64_t n_samples,
+                                 const uint64_t *out_samples, const int64_t *n_out) {
+    if (!amps || !n_out || (n_samples > 0 && !out_samples)) fail(RQC_EINVAL, "null argument");
+    if (n_qubits < 1 || n_qubits > 64) fail(RQC_EINVAL, "n_qubits must be 1..64");
+    if (n_open < 0 || n_open > n_qubits || n_open > 30 || (n_open > 0 && !open_qubits))
+        fail(RQC_EINVAL, "bad open qubits");
+    if (log2_NA < 0 || log2_NA > n_open) fail(RQC_EINVAL, "log2_NA must be within the open batch");
+    if (!(alpha > 0) || !(F_norm > 0)) fail(RQC_EINVAL, "alpha and F_norm must be positive");
+    if (n_samples < 0 || n_batches < 0 || pick_steps < 0) fail(RQC_EINVAL, "negative count");
+    if (pick_steps > 0 && (n_batches != 1 || n_open != n_qubits))
+        fail(RQC_EINVAL, "pick mode needs one batch with every qubit open");
+    if (n_batches > 0 && !fixed_bits) fail(RQC_EINVAL, "null fixed_bits");
+    for (int b = 0; b < n_open; b++)
+        if (open_qubits[b] < 0 || open_qubits[b] >= n_qubits) fail(RQC_EINVAL, "open qubit out of range");
+    if (pick_steps == 0 && n_batches > ((int64_t)1 << 40)) fail(RQC_EINVAL, "too many batches");
+    return pick_steps > 0 ? pick_steps : n_batches * ((int64_t)1 << (n_open - log2_NA));
+}
+
 rqc_status rqc_rejection_sample(const void *amps, const uint64_t *fixed_bits, int64_t n_batches,
                                 const int32_t *open_qubits, int32_t n_open, int32_t log2_NA, int32_t n_qubits,
                                 double alpha, double F_norm, uint64_t seed, uint64_t batch_index_base,
                                 int64_t pick_steps, int64_t n_samples, uint64_t *out_samples, int64_t *n_out,
                                 rqc_sample_stats *stats, void *hip_stream) {
     rqc_status st = guard([&] {
-        if (!amps || !n_out || (n_samples > 0 && !out_samples)) fail(RQC_EINVAL, "null argument");
-        if (n_qubits < 1 || n_qubits > 64) fail(RQC_EINVAL, "n_qubits must be 1..64");
-        if (n_open < 0 || n_open > n_qubits || n_open > 30 || (n_open > 0 && !open_qubits))
-            fail(RQC_EINVAL, "bad open qubits");
-        if (log2_NA < 0 || log2_NA > n_open) fail(RQC_EINVAL, "log2_NA must be within the open batch");
-        if (!(alpha > 0) || !(F_norm > 0)) fail(RQC_EINVAL, "alpha and F_norm must be positive");
-        if (n_samples < 0 || n_batches < 0 || pick_steps < 0) fail(RQC_EINVAL, "negative count");
-        if (pick_steps > 0 && (n_batches != 1 || n_open != n_qubits))
-            fail(RQC_EINVAL, "pick mode needs one batch with every qubit open");
-        if (n_batches > 0 && !fixed_bits) fail(RQC_EINVAL, "null fixed_bits");
-        for (int b = 0; b < n_open; b++)
-            if (open_qubits[b] < 0 || open_qubits[b] >= n_qubits) fail(RQC_EINVAL, "open qubit out of range");
+        const int64_t items = check_sample_args(amps, fixed_bits, n_batches, open_qubits, n_open, log2_NA, n_qubits,
+                                                alpha, F_norm, pick_steps, n_samples, out_samples, n_out);
         hipStream_t s = (hipStream_t)hip_stream;
-        const int64_t items = pick_steps > 0 ? pick_steps : n_batches * ((int64_t)1 << (n_open - log2_NA));
         StreamScratch &sc = stream_scratch(s);
         std::lock_guard<std::mutex> lk(sc.mu);
         void *w = scratch_reserve(sc, sampler_scratch_bytes(items, n_batches, n_open));
         const hipError_t e = run_sampler((const float2 *)amps, fixed_bits, n_batches, open_qubits, n_open, log2_NA,
                                          n_qubits, alpha, F_norm, seed, batch_index_base, pick_steps, n_samples,
                                          out_samples, n_out, stats, w, s);
+        if (e != hipSuccess) fail(RQC_EDEVICE, std::string("sampler: ") + hipGetErrorString(e));
+    });
+    if (st == RQC_OK && *n_out < n_samples) {
+        g_err = "fewer accepted samples than requested";
+        return RQC_ESHORT;
+    }
+    return st;
+}
+
+rqc_status rqc_rejection_sample_static(const void *amps, const uint64_t *fixed_bits, int64_t n_batches,
+                                       const int32_t *open_qubits, int32_t n_open, int32_t log2_NA,
+                                       int32_t n_qubits, double alpha, double F_norm, uint64_t seed,
+                                       uint64_t batch_index_base, int64_t pick_steps, int64_t n_samples,
+                                       uint64_t *out_samples, int64_t *n_out, rqc_sample_stats *stats,
+                                       void *hip_stream) {
+    rqc_status st = guard([&] {
+        const int64_t items = check_sample_args(amps, fixed_bits, n_batches, open_qubits, n_open, log2_NA, n_qubits,
+                                                alpha, F_norm, pick_steps, n_samples, out_samples, n_out);
+        const size_t need = sampler_scratch_bytes(items, n_batches, n_open);
+        if (need > (size_t)RQC_SAMPLE_STATIC_SCRATCH_BYTES)
+            fail(RQC_EINVAL, "the call needs " + std::to_string(need) + " bytes of scratch; the fixed array holds " +
+                                 std::to_string((size_t)RQC_SAMPLE_STATIC_SCRATCH_BYTES));
+        void *w = nullptr;
+        std::mutex *call_mu = nullptr;
+        HIP_OK(static_scratch(&w, &call_mu));
+        // one call at a time per device: the array is shared, and each call has
+        // finished with it (the sampler synchronises its stream) when it returns
+        std::lock_guard<std::mutex> lk(*call_mu);
+        const hipError_t e = run_sampler((const float2 *)amps, fixed_bits, n_batches, open_qubits, n_open, log2_NA,
+                                         n_qubits, alpha, F_norm, seed, batch_index_base, pick_steps, n_samples,
+                                         out_samples, n_out, stats, w, (hipStream_t)hip_stream);
         if (e != hipSuccess) fail(RQC_EDEVICE, std::string("sampler: ") + hipGetErrorString(e));
     });
     if (st == RQC_OK && *n_out < n_samples) {

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -186,12 +187,12 @@ size_t sampler_scratch_bytes(int64_t n_items, int64_t n_batches, int n_open) {
 hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batches, const int32_t *open_q,
                        int n_open, int log2_na, int n_qubits, double alpha, double f_norm, uint64_t seed,
                        uint64_t base, int64_t pick_steps, int64_t n_samples, uint64_t *out, int64_t *n_out,
-                       rqc_sample_stats *stats, void *scratch, hipStream_t s) {
+                       rqc_sample_stats *stats, void *work, hipStream_t s) {
     const int pick = pick_steps > 0;
     const int64_t sub_per_batch = (int64_t)1 << (n_open - log2_na);
     const int64_t n_items = pick ? pick_steps : n_batches * sub_per_batch;
     const int log2_nb = n_qubits - log2_na;
-    char *w = (char *)scratch;
+    char *w = (char *)work;
     SubResult *res = (SubResult *)w;
     w += align256((size_t)std::max<int64_t>(n_items, 1) * sizeof(SubResult));
     uint64_t *d_fixed = (uint64_t *)w;
@@ -229,6 +230,35 @@ hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batc
         stats->eps_J = h.eps_J;
         stats->p_total = h.p_total;
     }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------ fixed scratch
+// The scratch of rqc_rejection_sample_static: one array per device, held until
+// the process ends.  On the host its name is a stand-in, not a device address,
+// so host code never passes it to a kernel or a copy; it takes the address
+// hipGetSymbolAddress returns for the current device (each device holds its own
+// copy of the array at its own address) and passes that.
+static __device__ __align__(256) unsigned char scratch[RQC_SAMPLE_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_static_mu;
+static void *g_static_ptr[kMaxDevices] = {};
+static std::mutex g_static_call_mu[kMaxDevices];
+
+hipError_t static_scratch(void **ptr, std::mutex **call_mu) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_ptr[dev] = p;
+    }
+    *ptr = g_static_ptr[dev];
+    *call_mu = &g_static_call_mu[dev];
     return hipSuccess;
 }
 

@@ -124,6 +124,10 @@ _sig = {
                              ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                              ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
                              ctypes.POINTER(SampleStats), _P],
+    "rqc_rejection_sample_static": [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(SampleStats), _P],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -327,6 +331,23 @@ def rejection_sample(amps, fixed_bits, open_qubits, n_qubits, n_samples, out_sam
                                             _ptr(out_samples), ctypes.byref(n_out), ctypes.byref(st),
                                             _stream(stream)), allow=(ESHORT,))
     return n_out.value, st.as_dict(), code
+
+
+def rejection_sample_static(amps, fixed_bits, open_qubits, n_qubits, n_samples, out_samples, alpha=2.0,
+                            F_norm=1.0, seed=7, batch_index_base=0, log2_NA=6, pick_steps=0, stream=None):
+    """rejection_sample with its scratch in the library's fixed device array
+    (no allocation).  Returns (n_out, stats dict, status)."""
+    n_out = ctypes.c_int64()
+    st = SampleStats()
+    code = _check(_lib.rqc_rejection_sample_static(_ptr(amps), _u64(list(fixed_bits)), len(fixed_bits),
+                                                   _i32(list(open_qubits)), len(open_qubits), log2_NA, n_qubits,
+                                                   alpha, F_norm, seed, batch_index_base, pick_steps, n_samples,
+                                                   _ptr(out_samples), ctypes.byref(n_out), ctypes.byref(st),
+                                                   _stream(stream)), allow=(ESHORT,))
+    return n_out.value, st.as_dict(), code
+
+
+SAMPLE_STATIC_SCRATCH_BYTES = 8 << 20  # RQC_SAMPLE_STATIC_SCRATCH_BYTES
 
 
 def kernel_cgemm(A, B, C, batch, M, N, K, a_kfast=1, b_nfast=1, precision=C64, stream=None):
