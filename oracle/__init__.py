@@ -14,6 +14,8 @@ with the HIP library:
                (Sec. II.A-C, Eqs. 3-5, 10), the fidelity bound (Eq. 9)
   partial.py   orthogonal slice decomposition psi = sum_i psi_i, norms R,
                SlicedVertexSelect and slice selection (Sec. I.A-C, Appendix B)
+  spoof.py     linear-XEB spoofing: batch size, top selection, the XEB of the
+               kept set and its expectation (Sec. III.B, Eqs. 11-12, Appendix A)
 
 Only tests/, __graft_entry__.smoke() and bench.py's CPU-baseline leg may import
 this package.  Nothing in the product path does.
