@@ -89,3 +89,15 @@ def test_traffic_record_only_for_its_plan(cls):
     assert bench.measured_traffic(cls, key.replace("tree=", "tree=x")) is None
     assert bench.measured_traffic(cls, key.replace("mid:", "tiny:")) is None
     assert bench.measured_traffic(cls, None) is None
+
+
+def test_gate_count_of_the_53_qubit_circuit():
+    """The CPU baseline scales its per-gate time by the 53-qubit circuit's gate
+    count, taken from the oracle's parser (its state vector code refuses
+    circuits that wide)."""
+    import synthetic
+    cfg = synthetic.CONFIGS["large"]
+    text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    lines = [ln.split() for ln in text.splitlines()]
+    want = sum(1 for w in lines if w and w[0] in ("sx", "sy", "sw", "fsim"))
+    assert bench.gate_count(text) == want > 1000
