@@ -101,7 +101,7 @@ def kernel_roofline(op_recs, workload=None):
     minimum time, and `binding_frac` = sum of per-op minimum times / measured."""
     classes = {}
     for r in op_recs:
-        if r["cls"] == "sample":
+        if r["cls"] in ("sample", "select"):
             continue
         c = classes.setdefault(r["cls"], dict(seconds=0.0, flops=0.0, bytes=0.0, exec_flops=0.0, launches=0,
                                               tmin=0.0, t_flop=0.0, t_byte=0.0, kinds=set()))
@@ -166,10 +166,11 @@ def class_seconds(op_recs):
 class SamplerTimer:
     """HIP events around the sampler calls on the stream they run on (the
     sampler entry point synchronises that stream before returning, so the
-    second event also covers the host's return from the call)."""
+    second event also covers the host's return from the call).  `cls` names
+    the timed class in the per-op records (the top selection uses it too)."""
 
-    def __init__(self, torch, stream):
-        self.torch, self.stream = torch, stream
+    def __init__(self, torch, stream, cls="sample"):
+        self.torch, self.stream, self.cls = torch, stream, cls
         self.pairs = []
 
     def __enter__(self):
@@ -187,7 +188,7 @@ class SamplerTimer:
     def record(self):
         self.torch.cuda.synchronize()
         sec = sum(a.elapsed_time(b) for a, b in self.pairs) * 1e-3
-        return {"cls": "sample", "op": -1, "launches": len(self.pairs), "seconds": sec, "flops": 0.0,
+        return {"cls": self.cls, "op": -1, "launches": len(self.pairs), "seconds": sec, "flops": 0.0,
                 "bytes": 0.0, "exec_flops": 0.0, "exec_kind": 0}
 
 
@@ -374,6 +375,7 @@ LARGE_F = 2.0 ** -18     # target fidelity: the kept fraction 2^10 / 2^28
 LARGE_SHARE = 1 << 10    # slices in one GPU's share
 LARGE_TRIALS = 4096      # tree-search trials per seed
 LARGE_SEEDS = 4          # seeds searched; the best estimated job time is kept
+LARGE_ANNEAL = 1_000_000 # annealing moves per refined tree, from the best seed
 
 
 def plan_large(rqc, circ, open_q, args):
@@ -382,17 +384,27 @@ def plan_large(rqc, circ, open_q, args):
     2^|I| slices) wins.  Returns (path, legs, record)."""
     best = None
     tried = []
-    for seed in range(args.large_seeds):
+
+    def consider(seed, anneal):
+        nonlocal best
         p = rqc.plan_create(circ, open_q, max_log2_tensor=30, n_sliced_target=-1, max_log2_batched=30,
-                            path_trials=args.path_trials, path_seed=seed, target_fidelity=LARGE_F, dry_run=1)
+                            path_trials=args.path_trials, path_seed=seed, target_fidelity=LARGE_F, dry_run=1,
+                            anneal_iters=anneal)
         path, legs = rqc.plan_path(p), rqc.plan_sliced_legs(p)
         # the same tree and legs with every leg summed: its estimate covers all slices
         q = rqc.plan_create(circ, open_q, path=path, sliced_legs=legs, max_log2_batched=30, dry_run=1)
         qi = rqc.plan_info(q)
-        tried.append({"seed": seed, "n_sliced": len(legs), "est_seconds_all_slices": qi["est_seconds"],
+        tried.append({"seed": seed, "anneal_iters": anneal, "n_sliced": len(legs),
+                      "est_seconds_all_slices": qi["est_seconds"],
                       "flops_per_slice": qi["flops_per_batch"] / qi["n_slices"]})
         if best is None or qi["est_seconds"] < best[2]["est_seconds_all_slices"]:
             best = (path, legs, tried[-1])
+
+    for seed in range(args.large_seeds):
+        consider(seed, 0)
+    # simulated annealing of tree and slicing from the best seed's search
+    if getattr(args, "anneal_iters", 0) > 0:
+        consider(best[2]["seed"], args.anneal_iters)
     return best[0], best[1], tried
 
 
@@ -538,7 +550,7 @@ def run_large(args, rqc, torch):
         "path_roofline": path_roofline(op_recs, elapsed),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_large(text, share_s, o)
+        line["cpu_baseline"] = cpu_baseline_large(text, o, f"the GPU share time is {share_s:.3g} s at F = 2^-18")
     return line
 
 
@@ -549,7 +561,7 @@ def gate_count(text):
     return len(oc.parse(text).gates)
 
 
-def cpu_baseline_large(text, share_s, o, budget_s=20.0):
+def cpu_baseline_large(text, o, gpu_note, budget_s=20.0):
     """The oracle's FP64 state vector on all host cores cannot hold 53 qubits:
     it is timed per gate at 28 qubits over a prefix of this circuit's gate
     list restricted to the first 28 qubits, and extrapolated by 2^25 in state
@@ -593,27 +605,147 @@ def cpu_baseline_large(text, share_s, o, budget_s=20.0):
     return {"value": (1 << o) / t_full, "unit": "amplitudes/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 state vector of the first {n_small} qubits over {g} gates ({dt:.1f} s), per-gate time "
                       f"scaled by 2^{53 - n_small} to 53 qubits and by {n_gates} gates (extrapolated, {t_full:.3g} s "
-                      f"per 2^{o}-amplitude batch at fidelity 1; the GPU share time is {share_s:.3g} s at F = 2^-18)"}
+                      f"per 2^{o}-amplitude batch at fidelity 1; {gpu_note})"}
+
+
+# Linear-XEB spoofing (Sec. III.B, Table IV's first row): 53 qubits, 12 cycles,
+# one batch of 2^25 amplitudes at the slicing ratio f = 1.4 %, the top tenth kept
+SPOOF = dict(rows=6, cols=9, removed=((0, 4),), cycles=12, seed=0, b=25, f=0.014, r=0.1, trials=4096)
+
+
+def spoof_open_window(rqc, circ, n, b, trials=128):
+    """Sec. III.B step 2: the b free outputs with the least contraction cost,
+    searched over windows of b consecutive qubits (the planner's time estimate
+    of the full batch, host-only plans)."""
+    best = None
+    for start in range(0, n - b + 1):
+        open_q = list(range(start, start + b))
+        p = rqc.plan_create(circ, open_q, max_log2_tensor=30, n_sliced_target=-1, max_log2_batched=30,
+                            path_trials=trials, path_seed=0, dry_run=1)
+        est = rqc.plan_info(p)["est_seconds"]
+        if best is None or est < best[1]:
+            best = (open_q, est)
+    return best[0]
+
+
+def run_spoof(args, rqc, torch):
+    """One step = the spoofing recipe for one batch: the 2^b amplitudes with
+    partial slicing at fidelity f (Sec. I.C, all of X x {0,1}^(|I|-|S|)), then
+    the top floor(r 2^b) of them selected on the GPU."""
+    torch.cuda.set_device(0)
+    cfg = SPOOF
+    text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    n = cfg["rows"] * cfg["cols"] - len(cfg["removed"])
+    circ = rqc.load_circuit(text)
+    b = cfg["b"]
+    t0 = time.perf_counter()
+    open_q = spoof_open_window(rqc, circ, n, b)
+    window_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = rqc.plan_create(circ, open_q, max_log2_tensor=30, n_sliced_target=-1, max_log2_batched=30,
+                           path_trials=cfg["trials"], path_seed=args.path_seed, target_fidelity=cfg["f"], profile=1)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = rqc.plan_info(plan)
+    S, X, R = rqc.plan_partial(plan)
+    count = int(np.floor(cfg["r"] * (1 << b)))
+    out = torch.empty((1, 1 << b, 2), dtype=torch.float32, device="cuda")
+    sel = torch.empty(count, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    sel_time = SamplerTimer(torch, stream, cls="select")
+
+    def step(i):
+        fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + i)]
+        rqc.contract_amplitudes(plan, fb, out, stream=stream)
+        with sel_time:
+            rqc.select_top(out, fb[0], open_q, n, count, sel, stream=stream)
+
+    for w in range(args.warmup):
+        step(w)
+    torch.cuda.synchronize()
+    rqc.plan_profile_reset(plan)
+    sel_time.reset()
+    lat = []
+    t_start = time.perf_counter()
+    for s_ in range(args.steps):
+        ts = time.perf_counter()
+        step(args.warmup + s_)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    elapsed = time.perf_counter() - t_start
+    op_recs = rqc.plan_profile_ops(plan) + [sel_time.record()]
+    step_s = elapsed / args.steps
+    F = info["fidelity"]
+    line = {
+        "metric": METRIC, "value": (1 << b) / step_s, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * step_s, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE["c64"], "data": "synthetic",
+        "samples_per_s": count / step_s, "tflops": info["flops_per_batch"] / step_s / 1e12,
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "spoof": {"b": b, "samples_per_batch": count, "r": count / (1 << b), "target_fidelity": cfg["f"],
+                  "F": F, "k": len(S), "X": len(X), "job_slices": info["n_slices"],
+                  "expected_xeb_eq11": -F * float(np.log(count / (1 << b))),
+                  "select_ms_per_step": 1e3 * op_recs[-1]["seconds"] / max(1, op_recs[-1]["launches"]),
+                  "note": "XEB of the kept set expected at -F ln r above the batch's own (Eq. (11)-(12)); "
+                          "the relation is checked against exact probabilities on 20-qubit circuits in the tests"},
+        "config": {"workload": f"spoof: 6x9 grid minus (0,4), 53 qubits, {cfg['cycles']} cycles; one batch of "
+                               f"2^{b} amplitudes on the {b} cheapest consecutive open qubits (from {open_q[0]}), "
+                               f"partial slicing at f = {cfg['f']} (k = {len(S)}, |X| = {len(X)}, "
+                               f"{info['n_slices']} slices); step = the batch + top-{count} selection",
+                   "qubits": n, "open_qubits": open_q, "flops_per_batch": info["flops_per_batch"],
+                   "gemm_flop_share": info["gemm_flop_share"], "max_log2_tensor": info["max_log2_tensor"],
+                   "plan_seconds": {"open_window_search": window_s, "plan_and_norms": plan_s},
+                   "tree_sha256": tree_digest(rqc, plan), "kernel_seconds": class_seconds(op_recs)},
+        "roofline": kernel_roofline(op_recs, None),
+        "path_roofline": path_roofline(op_recs, elapsed),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_large(text, b, f"the GPU batch time is {step_s:.3g} s at F = {F:.3g}")
+    return line
+
+
+
+# The serving workload: seeded random grid circuits of 20-40 qubits, 8-20
+# cycles, 2^6-2^13 amplitudes, half of them also asking for 1e3-1e4 samples,
+# half in bf16x3; requests whose plan costs more than SERVE_CAP flops are
+# refused and counted
+SERVE_KW = dict(shapes=((4, 5), (4, 6), (5, 5), (5, 6), (5, 7), (6, 6), (5, 8)), cycles=(8, 20), log2_amps=(6, 13),
+                samples=(1000, 10000), sample_frac=0.5, bf16_frac=0.5, min_log2_for_samples=13)
+SERVE_CAP = 2e13
+
+
+def serve_workload_text(n, kw, cap):
+    shapes = ", ".join(f"{r}x{c}" for r, c in kw["shapes"])
+    qubits = sorted(r * c for r, c in kw["shapes"])
+    return (f"serving: {n} seeded requests per load, grids {shapes} ({qubits[0]}..{qubits[-1]} qubits), "
+            f"{kw['cycles'][0]}..{kw['cycles'][1]} cycles, 2^{kw['log2_amps'][0]}..2^{kw['log2_amps'][1]} amplitudes, "
+            f"{int(100 * kw['sample_frac'])}% also asking for {kw['samples'][0]}..{kw['samples'][1]} samples "
+            f"(in batches of 2^{kw['min_log2_for_samples']}), "
+            f"{int(100 * kw['bf16_frac'])}% bf16x3; plan-cost cap {cap:.0e} flops (above it: refused)")
 
 
 def run_serve(args, torch):
     from paper_2112_15083_amd import serve
     torch.cuda.set_device(0)
-    kw = dict(shapes=((4, 5), (4, 6), (5, 5), (5, 6)), cycles=(8, 12), log2_amps=(6, 12), samples=(100, 400))
-    reqs = serve.synthetic_requests(args.serve_requests, seed=0, rate=None, **kw)
+    kw = dict(SERVE_KW)
+    n = args.serve_requests
+    t_all = time.perf_counter()
+    reqs = serve.synthetic_requests(n, seed=0, rate=None, **kw)
     # capacity: everything submitted at once
-    srv = serve.Server(n_streams=4, plan_workers=8)
+    srv = serve.Server(n_streams=4, plan_workers=16, plan_flops_cap=SERVE_CAP)
     t0 = time.perf_counter()
     res = [f.result() for f in [srv.submit(r) for _, r in reqs]]
     cap_s = time.perf_counter() - t0
+    cap_stats = dict(srv.stats)
     srv.shutdown()
     ok = [r for r in res if r.status == "ok"]
     max_rate = len(ok) / cap_s
+    print(f"capacity run: {len(ok)} served, {cap_stats['refused']} refused in {cap_s:.1f} s", flush=True)
     loads = {}
     for load in (0.5, 0.8, 1.0):
         rate = load * max_rate
-        reqs = serve.synthetic_requests(args.serve_requests, seed=1, rate=rate, **kw)
-        srv = serve.Server(n_streams=4, plan_workers=8)
+        reqs = serve.synthetic_requests(n, seed=1, rate=rate, **kw)
+        srv = serve.Server(n_streams=4, plan_workers=16, plan_flops_cap=SERVE_CAP)
         t0 = time.perf_counter()
         futs = []
         for t, r in reqs:
@@ -623,6 +755,7 @@ def run_serve(args, torch):
             futs.append(srv.submit(r))
         res = [f.result() for f in futs]
         wall = time.perf_counter() - t0
+        st = dict(srv.stats)
         srv.shutdown()
         ok = [r for r in res if r.status == "ok"]
         lat = [r.latency for r in ok]
@@ -631,12 +764,17 @@ def run_serve(args, torch):
                             "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                             "p99_ms": 1e3 * float(np.percentile(lat, 99)),
                             "amplitudes_per_s": amps / wall,
+                            "samples_per_s": sum(r.n_samples for r in ok) / wall,
                             "tflops": sum(r.flops for r in ok) / wall / 1e12,
-                            "refused": sum(r.status == "refused" for r in res),
-                            "errors": sum(r.status == "error" for r in res)}
-    return {"metric": METRIC, "workload": f"serving: {args.serve_requests} seeded requests per load, "
-            "4x5..5x6 grids, 8..14 cycles, 2^6..2^12 amplitudes, half with 1e3..4e3 samples, "
-            "half bf16x3", "capacity_rps": max_rate, "loads": loads}
+                            "served": len(ok), "refused": st["refused"], "short": st["short"],
+                            "errors": st["errors"], "work_units": st["units"],
+                            "plan_cache_hits": st["plan_cache_hits"], "extra_sampling_rounds": st["extra_rounds"],
+                            "qubits_served": [min(r_.n_qubits for _, r_ in reqs), max(r_.n_qubits for _, r_ in reqs)]}
+        print(f"load {load}: {len(ok)} served, p50 {loads[str(load)]['p50_ms']:.1f} ms, "
+              f"p99 {loads[str(load)]['p99_ms']:.1f} ms", flush=True)
+    return {"metric": METRIC, "workload": serve_workload_text(n, kw, SERVE_CAP), "requests_per_load": n,
+            "capacity_rps": max_rate, "capacity_run": {"seconds": cap_s, **cap_stats}, "loads": loads,
+            "wall_seconds": time.perf_counter() - t_all}
 
 
 def copy_calibration(torch):
@@ -655,7 +793,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="large", choices=["tiny", "mid", "precision", "large"])
+    ap.add_argument("--config", default="large", choices=["tiny", "mid", "precision", "large", "spoof"])
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path-trials", type=int, default=None,
@@ -667,10 +805,12 @@ def main():
                     help="slices of the 53-qubit share per step (the share is 1024 slices)")
     ap.add_argument("--large-seeds", type=int, default=LARGE_SEEDS,
                     help="tree-search seeds for the 53-qubit plan (best estimated job time kept)")
+    ap.add_argument("--anneal-iters", type=int, default=LARGE_ANNEAL,
+                    help="simulated-annealing moves per refined tree for the 53-qubit plan (0 = search only)")
     ap.add_argument("--target-fidelity", type=float, default=0.0)
     ap.add_argument("--partial-sliced", type=int, default=12)
     ap.add_argument("--serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-global-cache", dest="global_cache", action="store_false",
                     help="skip the global-cache measurement reported beside the headline value")
@@ -691,6 +831,9 @@ def main():
     from paper_2112_15083_amd import rqc
     if args.config == "large":
         print(json.dumps(run_large(args, rqc, torch)), flush=True)
+        return
+    if args.config == "spoof":
+        print(json.dumps(run_spoof(args, rqc, torch)), flush=True)
         return
     print(json.dumps(run_mid_like(args, rqc, torch)), flush=True)
 

@@ -150,6 +150,11 @@ typedef struct {
        those kernels against the oracle.  Slower; results agree to FP32
        rounding. */
     int32_t no_matrix_core_streams;
+    /* > 0: refine the best searched trees by simulated annealing of the tree
+       and of the sliced legs (Sec. I names it as the optimiser of T and I),
+       this many Metropolis moves each; the refined trees compete with the
+       searched ones by estimated time.  User-given legs are kept fixed. */
+    int32_t anneal_iters;
 } rqc_plan_opts;
 
 typedef struct {
@@ -273,6 +278,13 @@ rqc_status rqc_plan_sliced_legs(const rqc_plan *p, int32_t *legs, int32_t cap, i
    another plan can be built on the same tree (the path the Sec. I tree T is
    contracted along). */
 rqc_status rqc_plan_path(const rqc_plan *p, int32_t *pairs, int32_t cap, int32_t *count);
+/* The plan's launch program as text, one op per line in launch order
+   ("<op> <kind> <kernel> <depends on fixed bits> <flops> <bytes> <shape>";
+   kernel "mx-wide" is the matrix-core streaming tile in its 64-bit addressed
+   form, for tiles spanning tensors of 2^29 elements or more):
+   what each contraction step of the tree became.  buf (host) receives at most
+   cap bytes, NUL-terminated; *len the full size including the NUL. */
+rqc_status rqc_plan_describe(const rqc_plan *p, char *buf, size_t cap, size_t *len);
 /* Partial slicing results: S (variable ids, bit t of an index i = S[t]), the
    kept indices X in selection order, and R[0 .. 2^k) (host arrays; any may be
    NULL; caps are element counts). */
@@ -313,6 +325,29 @@ void rqc_plan_destroy(rqc_plan *p);
  */
 rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64_t n_slices,
                                    const uint64_t *fixed_bits, int64_t n_batches, void *out_amps,
+                                   void *out_f64, void *hip_stream);
+
+/*
+ * The same contraction in work units, for schedulers that interleave requests
+ * (the serving loop runs one unit of a request at a time, so a long request
+ * does not hold a stream for its whole duration):
+ *   rqc_contract_groups adds, for each of n_batches batches, the FP64 slice
+ *   sums of the plan's default slice groups [first_group, first_group +
+ *   n_groups) (groups in the plan's order; rqc_plan_info_t.n_groups of them)
+ *   into acc_f64, device complex128 [n_batches][2^n_open], unnormalised; a call
+ *   with first_group = 0 overwrites the accumulator instead of adding to it.
+ *   rqc_finalize_amplitudes then writes (1/sqrt(F)) times the accumulated sums
+ *   as complex64 to out_amps (and the FP64 values to out_f64 if non-null).
+ * Calls over consecutive group ranges from 0 to n_groups, in order, followed by
+ * rqc_finalize_amplitudes, give results bit-identical to one
+ * rqc_contract_amplitudes call with the default slice list (the FP64 running
+ * sum is carried in the accumulator).  A range beyond the list gives
+ * RQC_EINVAL.  Asynchronous on hip_stream, ordered after the plan's previous
+ * calls.
+ */
+rqc_status rqc_contract_groups(rqc_plan *p, int64_t first_group, int64_t n_groups, const uint64_t *fixed_bits,
+                               int64_t n_batches, void *acc_f64, void *hip_stream);
+rqc_status rqc_finalize_amplitudes(rqc_plan *p, const void *acc_f64, int64_t n_batches, void *out_amps,
                                    void *out_f64, void *hip_stream);
 
 /*
@@ -370,6 +405,24 @@ rqc_status rqc_rejection_sample_static(const void *amps, const uint64_t *fixed_b
                                        uint64_t batch_index_base, int64_t pick_steps, int64_t n_samples,
                                        uint64_t *out_samples, int64_t *n_out, rqc_sample_stats *stats,
                                        void *hip_stream);
+
+/*
+ * Linear-XEB spoofing (Sec. III.B, step 4): the `count` bitstrings of one
+ * computed open batch with the largest probabilities.
+ *   amps: device complex64 [2^n_open], a batch as rqc_contract_amplitudes
+ *     writes it (under partial slicing, the approximate amplitudes of step 3).
+ *   p_t = (double)re^2 + (double)im^2 (squares exact, one rounding); the selection is every t with
+ *     p_t > T and, among the t with p_t = T, the smallest ones, where T is the
+ *     count-th largest p_t; so it is unique.
+ *   out_samples: device uint64 [count], the selected bitstrings in ascending
+ *     batch index t (fixed_bits on the other qubits, as in
+ *     rqc_contract_amplitudes).
+ *   0 <= count <= 2^n_open (else RQC_EINVAL); open_qubits (host) distinct.
+ * Asynchronous on hip_stream; uses the per-stream scratch block (a few bytes
+ * per 4096 amplitudes).
+ */
+rqc_status rqc_select_top(const void *amps, uint64_t fixed_bits, const int32_t *open_qubits, int32_t n_open,
+                          int32_t n_qubits, int64_t count, uint64_t *out_samples, void *hip_stream);
 
 /*
  * Kernel-level primitives (the contraction steps of Sec. I run on these; they

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librqc.so")
 
-SOURCES = ["circuit.cpp", "tree.cpp", "lower.cpp", "plan.cpp", "kernels.hip", "sampler.hip", "runtime.hip"]
+SOURCES = ["circuit.cpp", "tree.cpp", "anneal.cpp", "lower.cpp", "plan.cpp", "kernels.hip", "sampler.hip", "select.hip",
+           "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
@@ -29,8 +30,8 @@ def _flags(src: str):
     f = list(COMMON)
     if src.endswith(".hip"):
         f = ["-x", "hip"] + f + DEVICE
-    if src == "sampler.hip":
-        f.append("-ffp-contract=off")  # exact sampler arithmetic, see sampler.hip
+    if src in ("sampler.hip", "select.hip"):
+        f.append("-ffp-contract=off")  # exact FP64 probabilities, see sampler.hip / select.hip
     return f
 
 

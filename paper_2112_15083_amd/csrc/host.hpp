@@ -94,6 +94,15 @@ struct SearchResult {
     std::vector<int> sliced;
     double log2cost = 0;
 };
+// Time-like cost of one pairwise step of ranks ra, rb (operands), runion
+// (their union) and rc (result): multiply-adds plus weighted elements moved.
+double step_time_cost(int ra, int rb, int runion, int rc);
+// Simulated annealing of a tree and its sliced legs (anneal.cpp): `iters`
+// Metropolis moves from (t, sliced); slicing moves only if slice_moves (and
+// keeping |sliced| when n_target >= 0); every state within max_log2_tensor.
+SearchResult anneal_tree(const Tree &t, const std::vector<int> &sliced, const std::vector<Legs> &leaf_legs,
+                         int n_vars, const std::vector<char> &kept, const std::vector<char> &forbidden,
+                         int max_log2_tensor, bool slice_moves, int n_target, int iters, uint64_t seed);
 // The reconfigured best trials (a sixteenth of `trials`, at least 8), best proxy cost first.
 std::vector<SearchResult> search_tree(const std::vector<Legs> &leaf_legs, int n_vars, const std::vector<char> &kept,
                                       const std::vector<char> &forbidden, const std::vector<int> *user_sliced,
@@ -185,6 +194,7 @@ struct StreamOp {
     int rc, kc, nr, nf;
     int tile_l = -1; // >= 0: tiled kernel with 2^tile_l r per tile
     int mx = 0;      // 1: matrix-core tiled kernel
+    int wide = 0;    // mx: a tile spans 2^29 elements or more (64-bit addressed form)
     int lk = 0;      // 1: matrix-core long-contraction kernel
     int lk_split = 0;
     int mx2 = 0;     // 1: fused pair (then b2 is B2, kc2 / nf2 the second step's)
@@ -304,6 +314,9 @@ struct PlanCore {
     };
     std::vector<Candidate> candidates;
 };
+
+// Text table of the plan's launch program, one op per line.
+std::string describe_program(const PlanCore &p);
 
 // Contraction tree and sliced legs (user path/legs or the randomised search).
 // With partial slicing (lc non-null, no user path or legs), the searched

@@ -278,7 +278,10 @@ constexpr int mx_waves(int KC, int NC) {
            : (KC >= 3 && NC == 4) ? 3 : 4;
 }
 
-template <int KC, int NC>
+// WIDE: tiles whose elements span 2^29 or more (tensors of 2^30 elements, 8
+// GiB): offsets are held in elements and each access is a global load or
+// store at a 64-bit address, instead of a buffer access at a 32-bit byte offset.
+template <int KC, int NC, bool WIDE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_waves(KC, NC)))) k_stream_mx(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                    float2 *__restrict__ C, const BitMap *__restrict__ maps, int nr,
                                                    int nf, int L) {
@@ -307,14 +310,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_wav
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int ea = 2 * ((tid + 256 * k) & (hA - 1));
-        oA[k] = (uint32_t)map_apply(maps[SM_EA], ea) * 8u;
+        oA[k] = (uint32_t)map_apply(maps[SM_EA], ea) * (WIDE ? 1u : 8u);
         sA[k] = (uint32_t)(map_apply(maps[SM_ER], ea) * KP + map_apply(maps[SM_EY], ea)) |
                 (uint32_t)(map_apply(maps[SM_ER], ea + 1) * KP + map_apply(maps[SM_EY], ea + 1)) << 16;
     }
 #pragma unroll
     for (int k = 0; k < CPT; k++) {
         const int ec = 2 * ((tid + 256 * k) & (hC - 1));
-        oC[k] = (uint32_t)map_apply(maps[SM_EC], ec) * 8u;
+        oC[k] = (uint32_t)map_apply(maps[SM_EC], ec) * (WIDE ? 1u : 8u);
         sC[k] = (uint32_t)(map_apply(maps[SM_ER2], ec) * FP + map_apply(maps[SM_EF], ec)) |
                 (uint32_t)(map_apply(maps[SM_ER2], ec + 1) * FP + map_apply(maps[SM_EF], ec + 1)) << 16;
     }
@@ -332,9 +335,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_wav
     u32x4 pa0[4], pa1[4];
     const int64_t G = gridDim.x;
     auto load = [&](u32x4 (&pa)[4], int64_t tt) {
-        const __amdgpu_buffer_rsrc_t r = tile_rsrc(A + map_apply(maps[SM_RA], tt << L));
+        if constexpr (WIDE) {
+            const float2 *base = A + map_apply(maps[SM_RA], tt << L);
 #pragma unroll
-        for (int k = 0; k < 4; k++) pa[k] = __builtin_amdgcn_raw_buffer_load_b128(r, oA[k], 0, 0);
+            for (int k = 0; k < 4; k++) pa[k] = *reinterpret_cast<const u32x4 *>(base + oA[k]);
+        } else {
+            const __amdgpu_buffer_rsrc_t r = tile_rsrc(A + map_apply(maps[SM_RA], tt << L));
+#pragma unroll
+            for (int k = 0; k < 4; k++) pa[k] = __builtin_amdgcn_raw_buffer_load_b128(r, oA[k], 0, 0);
+        }
     };
     load(pa0, t);
     load(pa1, t + G < n_tiles ? t + G : t);
@@ -397,12 +406,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_wav
             }
         }
         __syncthreads();
-        const __amdgpu_buffer_rsrc_t w = tile_rsrc(C + map_apply(maps[SM_RC], r0));
+        if constexpr (WIDE) {
+            float2 *cbase = C + map_apply(maps[SM_RC], r0);
 #pragma unroll
-        for (int k = 0; k < CPT; k++) {
-            const float2 lo = TC[sC[k] & 0xffffu], hi = TC[sC[k] >> 16];
-            const u32x4 v = {__float_as_uint(lo.x), __float_as_uint(lo.y), __float_as_uint(hi.x), __float_as_uint(hi.y)};
-            __builtin_amdgcn_raw_buffer_store_b128(v, w, oC[k], 0, 0);
+            for (int k = 0; k < CPT; k++) {
+                const float2 lo = TC[sC[k] & 0xffffu], hi = TC[sC[k] >> 16];
+                const u32x4 v = {__float_as_uint(lo.x), __float_as_uint(lo.y), __float_as_uint(hi.x),
+                                 __float_as_uint(hi.y)};
+                *reinterpret_cast<u32x4 *>(cbase + oC[k]) = v;
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t w = tile_rsrc(C + map_apply(maps[SM_RC], r0));
+#pragma unroll
+            for (int k = 0; k < CPT; k++) {
+                const float2 lo = TC[sC[k] & 0xffffu], hi = TC[sC[k] >> 16];
+                const u32x4 v = {__float_as_uint(lo.x), __float_as_uint(lo.y), __float_as_uint(hi.x),
+                                 __float_as_uint(hi.y)};
+                __builtin_amdgcn_raw_buffer_store_b128(v, w, oC[k], 0, 0);
+            }
         }
     };
     for (;;) {
@@ -435,10 +456,11 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
     const int F = 1 << nf, nBt = 32 << nf;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, col = lane & 15;
-    const int64_t gi = (int64_t)blockIdx.x >> ks;
-    const int sp = blockIdx.x & ((1 << ks) - 1);
-    const int nch = 1 << (kc - 5 - ks), c0 = sp * nch;
-    const int64_t r0 = gi << 6;
+    const int nch = 1 << (kc - 5 - ks);
+    // work items: (row group, chunk range) pairs, dealt to a persistent grid
+    const int64_t n_items = (int64_t)1 << (nr - 6 + ks), G = gridDim.x;
+    int64_t item = blockIdx.x;
+    if (item >= n_items) return; // whole workgroup
     int offA[8], sA[8], offB[4], sB[4];
 #pragma unroll
     for (int k = 0; k < 8; k++) {
@@ -452,11 +474,11 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
         offB[k] = e < nBt ? (int)map_apply(maps[SM_EB], e) : 0;
         sB[k] = e < nBt ? 2 * (int)map_apply(maps[SM_BY], e) * SB + 2 * (int)map_apply(maps[SM_BF], e) : 0;
     }
-    // B' columns 2f + d with f >= F (fewer than 8 new indices) stay zero
+    // B' columns 2f + d with f >= F (fewer than 8 new indices) stay zero: the
+    // stagings only write the others
     for (int i = tid; i < 64 * SB; i += 256) TB[i] = 0.f;
-    const int64_t abase = map_apply(maps[SM_RA], r0), bbase = map_apply(maps[SM_RB], r0);
     float2 pa[8], pb[4];
-    auto load = [&](int ch) {
+    auto load = [&](int64_t abase, int64_t bbase, int ch) {
         const int64_t ya = abase + map_apply(maps[SM_YA], (int64_t)ch << 5);
         const int64_t yb = bbase + map_apply(maps[SM_YB], (int64_t)ch << 5);
 #pragma unroll
@@ -465,63 +487,89 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
         for (int k = 0; k < 4; k++)
             if (tid + 256 * k < nBt) pb[k] = B[yb + offB[k]];
     };
-    floatx4 acc[NC];
-#pragma unroll
-    for (int cb = 0; cb < NC; cb++) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    load(c0);
+    // the row group and first chunk of a work item
+    auto start = [&](int64_t it, int64_t &r0, int64_t &abase, int64_t &bbase, int &sp) {
+        r0 = (it >> ks) << 6;
+        sp = (int)(it & ((1 << ks) - 1));
+        abase = map_apply(maps[SM_RA], r0);
+        bbase = map_apply(maps[SM_RB], r0);
+    };
+    int64_t r0, abase, bbase;
+    int sp;
+    start(item, r0, abase, bbase, sp);
+    load(abase, bbase, sp * nch);
     __syncthreads(); // the zero fill of B' before its first staging
     // this lane's operands: A[row][k' = 4s + g], B'[k' = 4s + g][col + 16 cb]
     const float *arow = TA + (16 * wave + col) * RS + g;
     const float *bcol = TB + g * SB + col;
-    for (int ch = c0; ch < c0 + nch; ch++) {
+    for (;;) {
+        const int64_t next = item + G;
+        int64_t nr0 = 0, nabase = 0, nbbase = 0;
+        int nsp = 0;
+        if (next < n_items) start(next, nr0, nabase, nbbase, nsp);
+        floatx4 acc[NC];
 #pragma unroll
-        for (int k = 0; k < 8; k++) *reinterpret_cast<float2 *>(TA + sA[k]) = pa[k];
+        for (int cb = 0; cb < NC; cb++) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int c0 = sp * nch;
+        for (int ch = c0; ch < c0 + nch; ch++) {
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-            if (tid + 256 * k < nBt) {
-                *reinterpret_cast<float2 *>(TB + sB[k]) = pb[k];
-                *reinterpret_cast<float2 *>(TB + sB[k] + SB) = make_float2(-pb[k].y, pb[k].x);
+            for (int k = 0; k < 8; k++) *reinterpret_cast<float2 *>(TA + sA[k]) = pa[k];
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (tid + 256 * k < nBt) {
+                    *reinterpret_cast<float2 *>(TB + sB[k]) = pb[k];
+                    *reinterpret_cast<float2 *>(TB + sB[k] + SB) = make_float2(-pb[k].y, pb[k].x);
+                }
+            __syncthreads();
+            // the next chunk, or the next work item's first chunk
+            if (ch + 1 < c0 + nch) load(abase, bbase, ch + 1);
+            else if (next < n_items) load(nabase, nbbase, nsp * nch);
+#pragma unroll
+            for (int s = 0; s < NT; s++) {
+                const float a = arow[4 * s];
+#pragma unroll
+                for (int cb = 0; cb < NC; cb++)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bcol[4 * s * SB + 16 * cb], acc[cb], 0, 0, 0);
             }
-        __syncthreads();
-        if (ch + 1 < c0 + nch) load(ch + 1);
-#pragma unroll
-        for (int s = 0; s < NT; s++) {
-            const float a = arow[4 * s];
-#pragma unroll
-            for (int cb = 0; cb < NC; cb++)
-                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bcol[4 * s * SB + 16 * cb], acc[cb], 0, 0, 0);
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    if (ks == 0) {
-        // one chunk range: the 64 x F outputs go to C through LDS ([row][f],
-        // row stride F+2, in TA's space), written in C's memory order
-        const int FP = F + 2;
+        if (ks == 0) {
+            // one chunk range: the 64 x F outputs go to C through LDS ([row][f],
+            // row stride F+2, in TA's space), written in C's memory order
+            const int FP = F + 2;
 #pragma unroll
-        for (int cb = 0; cb < NC; cb++) {
-            const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
-            if (f < F) {
+            for (int cb = 0; cb < NC; cb++) {
+                const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
+                if (f < F) {
 #pragma unroll
-                for (int v = 0; v < 4; v++) TA[2 * ((16 * wave + 4 * g + v) * FP + f) + d] = acc[cb][v];
+                    for (int v = 0; v < 4; v++) TA[2 * ((16 * wave + 4 * g + v) * FP + f) + d] = acc[cb][v];
+                }
+            }
+            __syncthreads();
+            const float2 *TC = reinterpret_cast<const float2 *>(TA);
+            float2 *cb = C + map_apply(maps[SM_RC], r0);
+            const int nC = 64 << nf;
+            for (int e = tid; e < nC; e += 256)
+                cb[map_apply(maps[SM_EC], e)] = TC[map_apply(maps[SM_ER2], e) * FP + map_apply(maps[SM_EF], e)];
+            __syncthreads(); // TA is staged again by the next work item
+        } else {
+            float *Pf = reinterpret_cast<float *>(P);
+            const int64_t pbase = ((int64_t)sp << (nr + nf)) + ((r0 + 16 * wave + 4 * g) << nf);
+#pragma unroll
+            for (int cb = 0; cb < NC; cb++) {
+                const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
+                if (f < F) {
+#pragma unroll
+                    for (int v = 0; v < 4; v++) Pf[2 * (pbase + ((int64_t)v << nf) + f) + d] = acc[cb][v];
+                }
             }
         }
-        __syncthreads();
-        const float2 *TC = reinterpret_cast<const float2 *>(TA);
-        float2 *cb = C + map_apply(maps[SM_RC], r0);
-        const int nC = 64 << nf;
-        for (int e = tid; e < nC; e += 256)
-            cb[map_apply(maps[SM_EC], e)] = TC[map_apply(maps[SM_ER2], e) * FP + map_apply(maps[SM_EF], e)];
-        return;
-    }
-    float *Pf = reinterpret_cast<float *>(P);
-    const int64_t pbase = ((int64_t)sp << (nr + nf)) + ((r0 + 16 * wave + 4 * g) << nf);
-#pragma unroll
-    for (int cb = 0; cb < NC; cb++) {
-        const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
-        if (f < F) {
-#pragma unroll
-            for (int v = 0; v < 4; v++) Pf[2 * (pbase + ((int64_t)v << nf) + f) + d] = acc[cb][v];
-        }
+        if (next >= n_items) break;
+        item = next;
+        r0 = nr0;
+        abase = nabase;
+        bbase = nbbase;
+        sp = nsp;
     }
 }
 
@@ -711,16 +759,23 @@ static int64_t resident_blocks(const void *fn, size_t lds) {
     return cache[key] = (int64_t)per_cu * cus;
 }
 
-template <int KC, int NC>
-void launch_stream_mx_nc(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
-                         hipStream_t s) {
+template <int KC, int NC, bool WIDE>
+void launch_stream_mx_wide(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
+                           hipStream_t s) {
     const int L = op.tile_l;
     const int rsa = ((1 << KC) >= 4 ? 2 * (1 << KC) : 8) + 4; // floats per A row, as in the kernel
     const size_t lds = sizeof(float2) * (((size_t)1 << L) * (rsa / 2) + ((size_t)1 << L) * ((1 << op.nf) + 2));
     const int64_t tiles = (int64_t)1 << (op.nr - L);
-    const int64_t res = resident_blocks(reinterpret_cast<const void *>(&k_stream_mx<KC, NC>), lds);
+    const int64_t res = resident_blocks(reinterpret_cast<const void *>(&k_stream_mx<KC, NC, WIDE>), lds);
     const dim3 g((unsigned)std::min<int64_t>(tiles, res)), t(256);
-    hipLaunchKernelGGL((k_stream_mx<KC, NC>), g, t, lds, s, a, b, c, d_maps, op.nr, op.nf, L);
+    hipLaunchKernelGGL((k_stream_mx<KC, NC, WIDE>), g, t, lds, s, a, b, c, d_maps, op.nr, op.nf, L);
+}
+
+template <int KC, int NC>
+void launch_stream_mx_nc(const StreamOp &op, const BitMap *d_maps, const float2 *a, const float2 *b, float2 *c,
+                         hipStream_t s) {
+    if (op.wide) launch_stream_mx_wide<KC, NC, true>(op, d_maps, a, b, c, s);
+    else launch_stream_mx_wide<KC, NC, false>(op, d_maps, a, b, c, s);
 }
 
 template <int KC>
@@ -766,15 +821,18 @@ void launch_stream(const StreamOp &op, const BitMap *d_maps, const float2 *a, co
     if (kind == SK_LK) {
         if (op.kc < 6 || op.nf > 5 || op.nr < 6 || op.lk_split < 0 || op.lk_split > op.kc - 5 || (op.lk_split && !w))
             fail(RQC_EPLAN, "long streaming contraction exceeds the kernel's limits");
-        const int64_t blocks = (int64_t)1 << (op.nr - 6 + op.lk_split);
-        if (blocks > (int64_t)1 << 30) fail(RQC_EPLAN, "long streaming contraction grid too large");
-        const dim3 g((unsigned)blocks), t(256);
-        if (op.nf <= 3)
-            hipLaunchKernelGGL((k_stream_lk<1>), g, t, 0, s, a, b, w, c, d_maps, op.nr, op.kc, op.nf, op.lk_split);
-        else if (op.nf == 4)
-            hipLaunchKernelGGL((k_stream_lk<2>), g, t, 0, s, a, b, w, c, d_maps, op.nr, op.kc, op.nf, op.lk_split);
-        else
-            hipLaunchKernelGGL((k_stream_lk<4>), g, t, 0, s, a, b, w, c, d_maps, op.nr, op.kc, op.nf, op.lk_split);
+        const int64_t items = (int64_t)1 << (op.nr - 6 + op.lk_split);
+        auto go = [&](auto kern) {
+            // persistent grid: the per-workgroup set-up (offset tables, B' zero
+            // columns) is paid once per resident workgroup, not per row group
+            const int64_t res = resident_blocks(reinterpret_cast<const void *>(kern), 0);
+            hipLaunchKernelGGL(kern, dim3((unsigned)std::min<int64_t>(items, res)), dim3(256), 0, s, a, b, w, c,
+                               d_maps, op.nr, op.kc, op.nf, op.lk_split);
+        };
+        if (op.nf <= 3) go(k_stream_lk<1>);
+        else if (op.nf == 4) go(k_stream_lk<2>);
+        else go(k_stream_lk<4>);
+        const dim3 t(256);
         if (op.lk_split > 0) {
             const int64_t n = (int64_t)1 << (op.nr + op.nf);
             const dim3 g2((unsigned)std::min<int64_t>((n + 255) / 256, 256 * 16));

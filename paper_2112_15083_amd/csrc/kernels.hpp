@@ -70,6 +70,12 @@ hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batc
                        uint64_t base, int64_t pick_steps, int64_t n_samples, uint64_t *out,
                        int64_t *n_out, rqc_sample_stats *stats, void *work, hipStream_t s);
 
+// Top-count selection (select.hip): `work` is device memory of at least
+// select_scratch_bytes(2^n_open) bytes; open_q is a host array.  Asynchronous.
+size_t select_scratch_bytes(int64_t n);
+void launch_select_top(const float2 *amps, int n_open, const int32_t *open_q, uint64_t fixed, int64_t count,
+                       uint64_t *out, void *work, hipStream_t s);
+
 // The fixed device array of rqc_rejection_sample_static on the current device
 // (its address from hipGetSymbolAddress, looked up once per device) and the
 // lock that serialises the calls using it on that device.

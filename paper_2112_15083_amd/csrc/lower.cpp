@@ -802,13 +802,16 @@ struct Lowerer {
             op.m[SM_ER2] = make_map(er2);
             op.m[SM_EF] = make_map(ef);
             // the matrix-core kernel moves pairs of adjacent elements (tile bit 0
-            // must be tensor bit 0) at 32-bit byte offsets from the tile base
+            // must be tensor bit 0) at 32-bit offsets from the tile base: bytes, or
+            // elements in the wide form
             if (op.mx) {
                 int64_t spanA = 0, spanC = 0;
                 for (int v : PA) spanA += (int64_t)1 << v;
                 for (int v : PC) spanC += (int64_t)1 << v;
-                if (PA[0] != 0 || PC[0] != 0 || spanA >= ((int64_t)1 << 29) || spanC >= ((int64_t)1 << 29))
+                if (PA[0] != 0 || PC[0] != 0 || spanA >= ((int64_t)1 << 32) || spanC >= ((int64_t)1 << 32))
                     op.mx = 0;
+                // past 4 GiB of byte offsets: element offsets and 64-bit addresses
+                op.wide = spanA >= ((int64_t)1 << 29) || spanC >= ((int64_t)1 << 29);
             }
             if (!op.mx && L + op.nf > 11) op.tile_l = -1; // too large for the vector tile kernel
         }

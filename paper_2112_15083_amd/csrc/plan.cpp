@@ -2,7 +2,10 @@
 // (Appendix B, Alg. 1 and 2) and the final lowering of a plan.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
+#include <thread>
 
 #include "host.hpp"
 
@@ -159,6 +162,27 @@ int partial_k0(const rqc_plan_opts &o) {
     return o.partial_k > 0 ? o.partial_k : (int)std::ceil(3.0 - std::log2(o.target_fidelity));
 }
 
+// Simulated annealing of the best few searched results (tree, and sliced legs
+// when slice_moves), one host thread each; the annealed results join the list,
+// which is kept sorted by the proxy cost.
+static void anneal_results(std::vector<SearchResult> &rs, const std::vector<Legs> &leaf_legs, int nv,
+                           const std::vector<char> &kept, const std::vector<char> &forbidden,
+                           const rqc_plan_opts &o, bool slice_moves, uint64_t seed) {
+    if (o.anneal_iters <= 0 || rs.empty()) return;
+    const int n = std::min<int>(4, (int)rs.size());
+    std::vector<SearchResult> out(n);
+    std::vector<std::thread> pool;
+    for (int i = 0; i < n; i++)
+        pool.emplace_back([&, i] {
+            out[i] = anneal_tree(rs[i].tree, rs[i].sliced, leaf_legs, nv, kept, forbidden, o.max_log2_tensor,
+                                 slice_moves, o.n_sliced_target, o.anneal_iters, seed * 0x9E3779B97F4A7C15ull + i);
+        });
+    for (auto &t : pool) t.join();
+    for (auto &r : out) rs.push_back(std::move(r));
+    std::stable_sort(rs.begin(), rs.end(),
+                     [](const SearchResult &a, const SearchResult &b) { return a.log2cost < b.log2cost; });
+}
+
 void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std::vector<int> *user_sliced,
                const LightCones *lc) {
     const NetSpec &sp = p.spec;
@@ -232,6 +256,7 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
                 std::vector<SearchResult> part =
                     search_tree(reduced, nv, kept, forb, nullptr, p.opts.max_log2_tensor, p.opts.n_sliced_target,
                                 std::max(16, trials / n_first), p.opts.path_seed + 1 + (uint64_t)fi);
+                anneal_results(part, reduced, nv, kept, forb, p.opts, true, p.opts.path_seed + 1 + (uint64_t)fi);
                 for (auto &r : part) {
                     r.sliced.insert(r.sliced.begin(), S0.begin(), S0.end());
                     r.log2cost += (double)S0.size();
@@ -253,9 +278,11 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
             }
             rs = search_tree(reduced, nv, kept, sp.forbidden, user_sliced, p.opts.max_log2_tensor,
                              p.opts.n_sliced_target, trials, p.opts.path_seed);
+            anneal_results(rs, reduced, nv, kept, sp.forbidden, p.opts, false, p.opts.path_seed);
         } else {
             rs = search_tree(path_legs, nv, kept, sp.forbidden, nullptr, p.opts.max_log2_tensor,
                              p.opts.n_sliced_target, trials, p.opts.path_seed);
+            anneal_results(rs, path_legs, nv, kept, sp.forbidden, p.opts, true, p.opts.path_seed);
         }
         // the best by the proxy cost are lowered and compared by estimated time
         // (with the global cache, the per-batch time the proxy does not see)
@@ -515,6 +542,61 @@ void plan_finish(PlanCore &p) {
         I.n_fused += so.mx2;
         I.stream_kernels[stream_kernel(so)]++;
     }
+}
+
+// One line per op of the launch program: kind, kernel, shape, work.
+std::string describe_program(const PlanCore &p) {
+    static const char *sk_name[SK_COUNT] = {"mx2", "mx", "lk", "ky", "tile", "gen"};
+    const Program &pg = p.prog;
+    std::string out;
+    char line[512];
+    std::snprintf(line, sizeof line, "# op kind kernel dep flops bytes shape\n");
+    out += line;
+    for (size_t i = 0; i < pg.ops.size(); i++) {
+        const Op &op = pg.ops[i];
+        std::string shape;
+        const char *kind = "?", *kern = "-";
+        switch (op.kind) {
+        case OP_SMALL:
+            kind = "small";
+            kern = "small_trees";
+            std::snprintf(line, sizeof line, "trees=%zu lds_elems=%d", pg.small_trees.size(), pg.small_lds_elems);
+            shape = line;
+            break;
+        case OP_STREAM: {
+            const StreamOp &so = pg.streams[op.index];
+            kind = "stream";
+            kern = so.mx && so.wide ? "mx-wide" : sk_name[stream_kernel(so)];
+            std::snprintf(line, sizeof line, "rc=%d nr=%d kc=%d nf=%d tile_l=%d lk_split=%d kc2=%d nf2=%d", so.rc, so.nr,
+                          so.kc, so.nf, so.tile_l, so.lk_split, so.kc2, so.nf2);
+            shape = line;
+            break;
+        }
+        case OP_PERMUTE: {
+            const PermuteOp &po = pg.permutes[op.index];
+            kind = "permute";
+            kern = "permute";
+            std::snprintf(line, sizeof line, "r=%d", po.r);
+            shape = line;
+            break;
+        }
+        case OP_GEMM: {
+            const GemmOp &go = pg.gemms[op.index];
+            kind = "gemm";
+            kern = "cgemm";
+            std::snprintf(line, sizeof line, "batch=%lld M=%lld N=%lld K=%lld a_kfast=%d b_nfast=%d ksplit=%d",
+                          (long long)go.batch, (long long)go.M, (long long)go.N, (long long)go.K, go.a_kfast, go.b_nfast,
+                          go.ksplit);
+            shape = line;
+            break;
+        }
+        }
+        std::snprintf(line, sizeof line, "%zu %s %s %d %.6g %.6g ", i, kind, kern, op.dep, op.flops, op.bytes);
+        out += line;
+        out += shape;
+        out += "\n";
+    }
+    return out;
 }
 
 } // namespace rqc

@@ -318,11 +318,17 @@ void dump_plan(const rqc_plan &p) {
 
 // Run the plan's program for every (batch, slice group) pair.
 // Slice groups to run: an explicit list of looped-leg values, or 0 .. range-1.
+// Slice groups of a call: a list of looped values or the range 0 .. range-1,
+// of which the call runs [first, first + count) (cache slots are the absolute
+// positions).
 struct GroupList {
     const std::vector<uint64_t> *list = nullptr;
     uint64_t range = 0;
-    uint64_t size() const { return list ? list->size() : range; }
-    uint64_t operator[](uint64_t i) const { return list ? (*list)[i] : i; }
+    uint64_t first = 0, count = UINT64_MAX;
+    uint64_t full() const { return list ? list->size() : range; }
+    uint64_t size() const { return first >= full() ? 0 : std::min<uint64_t>(count, full() - first); }
+    uint64_t operator[](uint64_t i) const { return list ? (*list)[first + i] : first + i; }
+    uint64_t slot(uint64_t i) const { return first + i; }
 };
 
 GroupList default_groups(const rqc_plan *p) {
@@ -408,8 +414,12 @@ float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hi
 // Run the plan's program for every (batch, slice group) pair.  `is_default`:
 // the groups are the plan's default list (the global cache, if any, holds
 // their fixed-bit-independent parts; it is filled on the first such call).
+// acc_ext: null = a whole call (zero the plan's accumulator, sum the groups,
+// normalise into out_amps / out_f64); else the caller's FP64 accumulator
+// [n_batches][2^o], into which the groups' slices are added (overwritten
+// first when zero_ext), with no normalisation.
 void execute(rqc_plan *p, const GroupList &groups, bool is_default, const uint64_t *fixed_bits, int64_t n_batches,
-             void *out_amps, void *out_f64, hipStream_t s) {
+             void *out_amps, void *out_f64, hipStream_t s, double2 *acc_ext = nullptr, bool zero_ext = false) {
     const Program &pg = p->prog;
     const int n_open = (int)p->spec.open_vars.size();
     const int nl = (int)p->looped.size(), nb = (int)p->batched.size();
@@ -431,27 +441,30 @@ void execute(rqc_plan *p, const GroupList &groups, bool is_default, const uint64
         return vals;
     };
     if (cached && !p->cache_filled) {
-        for (uint64_t gi = 0; gi < groups.size(); gi++) run_group(p, RUN_INDEP, projection(0, groups[gi]), (int64_t)gi, s);
+        const GroupList all = default_groups(p);
+        for (uint64_t gi = 0; gi < all.size(); gi++) run_group(p, RUN_INDEP, projection(0, all[gi]), (int64_t)gi, s);
         p->cache_filled = true;
     }
     // calls with their own slice list use the spare cache block
     const int64_t spare = p->info.n_groups;
     for (int64_t bi = 0; bi < n_batches; bi++) {
-        {
+        double2 *acc = acc_ext ? acc_ext + bi * nout : p->d_acc;
+        if (!acc_ext || zero_ext) {
             Timer t(p, s, RQC_K_ACCUM, 0, 16.0 * nout);
-            launch_zero(p->d_acc, nout, s);
+            launch_zero(acc, nout, s);
         }
         for (uint64_t gi = 0; gi < groups.size(); gi++) {
             const ProjVals vals = projection(fixed_bits[bi], groups[gi]);
-            float2 *root = cached ? run_group(p, RUN_DEP, vals, (int64_t)gi, s) : run_group(p, RUN_ALL, vals, spare, s);
+            float2 *root = cached ? run_group(p, RUN_DEP, vals, (int64_t)groups.slot(gi), s)
+                                  : run_group(p, RUN_ALL, vals, spare, s);
             {
                 Timer t(p, s, RQC_K_ACCUM, 0, 8.0 * (double)(nout << nb) + 32.0 * nout);
-                launch_accumulate(root, p->d_rmaps, n_open, nb, p->d_acc, s);
+                launch_accumulate(root, p->d_rmaps, n_open, nb, acc, s);
             }
         }
-        {
+        if (!acc_ext) {
             Timer t(p, s, RQC_K_FINAL, 0, 16.0 * nout + 8.0 * nout);
-            launch_finalize(p->d_acc, nout, scale, (float2 *)out_amps + bi * nout,
+            launch_finalize(acc, nout, scale, (float2 *)out_amps + bi * nout,
                             out_f64 ? (double2 *)out_f64 + bi * nout : nullptr, s);
         }
     }
@@ -649,6 +662,19 @@ rqc_status rqc_plan_path(const rqc_plan *p, int32_t *pairs, int32_t cap, int32_t
     });
 }
 
+rqc_status rqc_plan_describe(const rqc_plan *p, char *buf, size_t cap, size_t *len) {
+    return guard([&] {
+        if (!p) fail(RQC_EINVAL, "null plan");
+        const std::string d = describe_program(*p);
+        if (len) *len = d.size() + 1;
+        if (buf && cap > 0) {
+            const size_t n = std::min(cap - 1, d.size());
+            std::memcpy(buf, d.data(), n);
+            buf[n] = 0;
+        }
+    });
+}
+
 rqc_status rqc_plan_partial(const rqc_plan *p, int32_t *S, int32_t capS, uint64_t *X, int64_t capX, double *R,
                             int64_t capR) {
     return guard([&] {
@@ -766,6 +792,52 @@ rqc_status rqc_contract_amplitudes(rqc_plan *p, const uint64_t *slice_ids, int64
     });
 }
 
+rqc_status rqc_contract_groups(rqc_plan *p, int64_t first_group, int64_t n_groups, const uint64_t *fixed_bits,
+                               int64_t n_batches, void *acc_f64, void *hip_stream) {
+    return guard([&] {
+        if (!p) fail(RQC_EINVAL, "null plan");
+        if (p->opts.dry_run) fail(RQC_EINVAL, "a dry-run plan cannot be executed");
+        if (n_batches < 0 || first_group < 0 || n_groups < 0) fail(RQC_EINVAL, "negative count");
+        GroupList gl = default_groups(p);
+        if ((uint64_t)first_group > gl.full() || (uint64_t)n_groups > gl.full() - (uint64_t)first_group)
+            fail(RQC_EINVAL, "group range beyond the plan's default slice list");
+        if (n_batches == 0) return;
+        if (!fixed_bits || !acc_f64) fail(RQC_EINVAL, "null fixed_bits or accumulator");
+        int dev = 0;
+        HIP_OK(hipGetDevice(&dev));
+        if (dev != p->device) fail(RQC_EDEVICE, "plan belongs to another device");
+        gl.first = (uint64_t)first_group;
+        gl.count = (uint64_t)n_groups;
+        execute(p, gl, true, fixed_bits, n_batches, nullptr, nullptr, (hipStream_t)hip_stream, (double2 *)acc_f64,
+                first_group == 0);
+    });
+}
+
+rqc_status rqc_finalize_amplitudes(rqc_plan *p, const void *acc_f64, int64_t n_batches, void *out_amps,
+                                   void *out_f64, void *hip_stream) {
+    return guard([&] {
+        if (!p) fail(RQC_EINVAL, "null plan");
+        if (p->opts.dry_run) fail(RQC_EINVAL, "a dry-run plan cannot be executed");
+        if (n_batches < 0) fail(RQC_EINVAL, "negative batch count");
+        if (n_batches == 0) return;
+        if (!acc_f64 || !out_amps) fail(RQC_EINVAL, "null accumulator or out_amps");
+        hipStream_t s = (hipStream_t)hip_stream;
+        const int64_t nout = (int64_t)1 << p->spec.open_vars.size();
+        const double scale = p->kappa / std::sqrt(p->F);
+        // ordered after the plan's previous calls (the accumulator they filled)
+        if (p->done_recorded) HIP_OK(hipStreamWaitEvent(s, p->done, 0));
+        for (int64_t bi = 0; bi < n_batches; bi++) {
+            Timer t(p, s, RQC_K_FINAL, 0, 16.0 * nout + 8.0 * nout);
+            launch_finalize((const double2 *)acc_f64 + bi * nout, nout, scale, (float2 *)out_amps + bi * nout,
+                            out_f64 ? (double2 *)out_f64 + bi * nout : nullptr, s);
+        }
+        HIP_OK(hipGetLastError());
+        if (!p->done) HIP_OK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+        HIP_OK(hipEventRecord(p->done, s));
+        p->done_recorded = true;
+    });
+}
+
 // Argument checks shared by the two sampling entry points; returns the number
 // of sampled items (sub-batches, or steps in pick mode).
 static int64_t check_sample_args(const void *amps, const uint64_t *fixed_bits, int64_t n_batches,
@@ -841,6 +913,33 @@ rqc_status rqc_rejection_sample_static(const void *amps, const uint64_t *fixed_b
         return RQC_ESHORT;
     }
     return st;
+}
+
+rqc_status rqc_select_top(const void *amps, uint64_t fixed_bits, const int32_t *open_qubits, int32_t n_open,
+                          int32_t n_qubits, int64_t count, uint64_t *out_samples, void *hip_stream) {
+    return guard([&] {
+        if (!amps || (count > 0 && !out_samples)) fail(RQC_EINVAL, "null argument");
+        if (n_qubits < 1 || n_qubits > 64) fail(RQC_EINVAL, "n_qubits must be 1..64");
+        if (n_open < 0 || n_open > n_qubits || n_open > 30 || (n_open > 0 && !open_qubits))
+            fail(RQC_EINVAL, "bad open qubits");
+        uint64_t seen = 0;
+        for (int b = 0; b < n_open; b++) {
+            if (open_qubits[b] < 0 || open_qubits[b] >= n_qubits) fail(RQC_EINVAL, "open qubit out of range");
+            if ((seen >> open_qubits[b]) & 1) fail(RQC_EINVAL, "open qubit repeated");
+            seen |= 1ull << open_qubits[b];
+        }
+        if (count < 0 || count > ((int64_t)1 << n_open)) fail(RQC_EINVAL, "count must be within the batch");
+        if (count == 0) return;
+        check_device();
+        hipStream_t s = (hipStream_t)hip_stream;
+        StreamScratch &sc = stream_scratch(s);
+        std::lock_guard<std::mutex> lk(sc.mu);
+        // stream order keeps later calls on s off this block until these
+        // kernels are done; other streams have blocks of their own
+        void *w = scratch_reserve(sc, select_scratch_bytes((int64_t)1 << n_open));
+        launch_select_top((const float2 *)amps, n_open, open_qubits, fixed_bits, count, out_samples, w, s);
+        HIP_OK(hipGetLastError());
+    });
 }
 
 rqc_status rqc_kernel_cgemm(const void *A, const void *B, void *C, int64_t batch, int64_t M, int64_t N, int64_t K,

@@ -101,7 +101,7 @@ double tree_log2_cost_sum(const Tree &t, const std::vector<Legs> &legs) {
 // operands are served from cache or LDS.
 static constexpr double kTraffic = 5.0;
 
-static double step_cost(int ra, int rb, int runion, int rc) {
+double step_time_cost(int ra, int rb, int runion, int rc) {
     return std::exp2((double)runion) +
            kTraffic * (std::exp2((double)ra) + std::exp2((double)rb) + std::exp2((double)rc));
 }
@@ -111,7 +111,7 @@ double tree_log2_time_cost(const Tree &t, const std::vector<Legs> &legs) {
     for (size_t s = 0; s < t.steps.size(); s++) {
         const Legs &A = legs[t.steps[s].first], &B = legs[t.steps[s].second];
         Legs u = merge_union(A, B);
-        acc += step_cost((int)A.size(), (int)B.size(), (int)u.size(),
+        acc += step_time_cost((int)A.size(), (int)B.size(), (int)u.size(),
                          (int)legs[t.n_leaves + s].size());
     }
     return std::log2(std::max(acc, 1.0));
@@ -376,7 +376,7 @@ Tree reconfigure_tree(const Tree &t, const std::vector<Legs> &leaf_legs, int n_v
                     int S1 = low | sub, S2 = S ^ S1;
                     if (S2) {
                         double c = cost[S1] + cost[S2] +
-                                   step_cost(lsz[S1], lsz[S2], mpop(mor(LG[S1], LG[S2])), lsz[S]);
+                                   step_time_cost(lsz[S1], lsz[S2], mpop(mor(LG[S1], LG[S2])), lsz[S]);
                         if (c < best) best = c, bs = S1;
                     }
                     if (sub == 0) break;
@@ -387,7 +387,7 @@ Tree reconfigure_tree(const Tree &t, const std::vector<Legs> &leaf_legs, int n_v
             // old cost of the same subtree
             double old = 0;
             for (int u : inner)
-                old += step_cost((int)legs[ca[u]].size(), (int)legs[cb[u]].size(),
+                old += step_time_cost((int)legs[ca[u]].size(), (int)legs[cb[u]].size(),
                                  (int)merge_union(legs[ca[u]], legs[cb[u]]).size(), (int)legs[u].size());
             if (cost[full] >= old * (1 - 1e-9)) continue;
             // rebuild: reuse the inner node ids, tnode stays the subtree root

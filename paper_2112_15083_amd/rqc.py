@@ -51,7 +51,8 @@ class PlanOpts(ctypes.Structure):
                 ("path_seed", ctypes.c_uint64), ("profile", ctypes.c_int32), ("dry_run", ctypes.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
                 ("global_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("no_stream_fusion", ctypes.c_int32), ("no_matrix_core_streams", ctypes.c_int32)]
+                ("no_stream_fusion", ctypes.c_int32), ("no_matrix_core_streams", ctypes.c_int32),
+                ("anneal_iters", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -111,12 +112,15 @@ _sig = {
     "rqc_plan_info": [_P, ctypes.POINTER(PlanInfo)],
     "rqc_plan_sliced_legs": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "rqc_plan_path": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "rqc_plan_describe": [_P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "rqc_plan_partial": [_P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int64],
     "rqc_plan_slices": [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
     "rqc_plan_profile": [_P, ctypes.POINTER(Profile)],
     "rqc_plan_profile_reset": [_P],
     "rqc_plan_profile_ops": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "rqc_contract_amplitudes": [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P],
+    "rqc_contract_groups": [_P, ctypes.c_int64, ctypes.c_int64, _P, ctypes.c_int64, _P, _P],
+    "rqc_finalize_amplitudes": [_P, _P, ctypes.c_int64, _P, _P, _P],
     "rqc_kernel_cgemm": [_P, _P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
     "rqc_kernel_permute": [_P, _P, ctypes.c_int32, _P, _P],
@@ -124,6 +128,7 @@ _sig = {
                              ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                              ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
                              ctypes.POINTER(SampleStats), _P],
+    "rqc_select_top": [_P, ctypes.c_uint64, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P],
     "rqc_rejection_sample_static": [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                     ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
@@ -256,6 +261,15 @@ def plan_info(p: Plan) -> dict:
     return info.as_dict()
 
 
+def plan_describe(p: Plan) -> str:
+    """The plan's launch program, one op per line (see rqc_plan_describe)."""
+    n = ctypes.c_size_t()
+    _check(_lib.rqc_plan_describe(p.handle, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(_lib.rqc_plan_describe(p.handle, buf, n.value, ctypes.byref(n)))
+    return buf.value.decode()
+
+
 def plan_sliced_legs(p: Plan):
     n = ctypes.c_int32()
     _check(_lib.rqc_plan_sliced_legs(p.handle, None, 0, ctypes.byref(n)))
@@ -320,6 +334,21 @@ def contract_amplitudes(p: Plan, fixed_bits, out_amps, out_f64=None, slice_ids=N
                                         len(fixed_bits), _ptr(out_amps), _ptr(out_f64), _stream(stream)))
 
 
+def contract_groups(p: Plan, first_group, n_groups, fixed_bits, acc_f64, stream=None):
+    """Add the FP64 sums of default slice groups [first_group, first_group +
+    n_groups) into acc_f64 (complex128 [n_batches][2^o]; overwritten when
+    first_group is 0).  Asynchronous."""
+    _check(_lib.rqc_contract_groups(p.handle, first_group, n_groups, _u64(list(fixed_bits)), len(fixed_bits),
+                                    _ptr(acc_f64), _stream(stream)))
+
+
+def finalize_amplitudes(p: Plan, acc_f64, n_batches, out_amps, out_f64=None, stream=None):
+    """Normalised complex64 (and optional FP64) amplitudes from an accumulator
+    filled by contract_groups.  Asynchronous."""
+    _check(_lib.rqc_finalize_amplitudes(p.handle, _ptr(acc_f64), n_batches, _ptr(out_amps), _ptr(out_f64),
+                                        _stream(stream)))
+
+
 def rejection_sample(amps, fixed_bits, open_qubits, n_qubits, n_samples, out_samples, alpha=2.0, F_norm=1.0,
                      seed=7, batch_index_base=0, log2_NA=6, pick_steps=0, stream=None):
     """Returns (n_out, stats dict, status) -- status is OK or ESHORT."""
@@ -348,6 +377,13 @@ def rejection_sample_static(amps, fixed_bits, open_qubits, n_qubits, n_samples, 
 
 
 SAMPLE_STATIC_SCRATCH_BYTES = 8 << 20  # RQC_SAMPLE_STATIC_SCRATCH_BYTES
+
+
+def select_top(amps, fixed_bits, open_qubits, n_qubits, count, out_samples, stream=None):
+    """The `count` bitstrings of one batch with the largest |amplitude|^2, in
+    ascending batch index (asynchronous)."""
+    _check(_lib.rqc_select_top(_ptr(amps), int(fixed_bits) & (2 ** 64 - 1), _i32(list(open_qubits)),
+                               len(open_qubits), n_qubits, count, _ptr(out_samples), _stream(stream)))
 
 
 def kernel_cgemm(A, B, C, batch, M, N, K, a_kfast=1, b_nfast=1, precision=C64, stream=None):

@@ -8,19 +8,26 @@ samples) flow through three stages that overlap:
            the circuit's structure (which gates act where, not which single-qubit
            gate), so they are searched once per structure and kept in a plan
            cache; requests whose plan exceeds the cost cap are refused;
-  admit    a planned request starts as soon as a stream slot is free and the
-           plans in flight plus its own workspace fit the HBM budget; requests
-           that can never fit are refused;
-  execute  each admitted request runs on its own HIP stream (contraction of its
-           batches, then sampling); completion is polled with events, results are
-           copied out and the request's workspace is released.  A sampling
-           request that accepted fewer samples than it asked for contracts
-           further batches (drawn by the request) on its stream and samples them
-           with the next sub-batch indices, until it has its count.
+  admit    a planned request is admitted as soon as the plans in flight plus its
+           own workspace fit the HBM budget; requests that can never fit are
+           refused;
+  execute  work units are (request, range of slice groups): a unit adds the
+           FP64 sums of its slice groups for all of the request's batches into
+           the request's accumulator (rqc_contract_groups).  Each free stream
+           takes the next unit of the earliest-arrived admitted request that has
+           none in flight (a request's units run one after another: they share
+           its plan's workspace), so a long request gives way to others between
+           units instead of holding a stream for its whole duration.  After its
+           last unit a request is normalised (rqc_finalize_amplitudes), copied
+           out and, if it asked for samples, sampled; a sampling request that
+           accepted fewer samples than it asked for contracts further batches
+           (drawn by the request) and samples them with the next sub-batch
+           indices, until it has its count.
 
-Every request's arithmetic is fixed by its plan (deterministic path search,
-fixed kernels and FP64 slice order), so its result does not depend on what
-else is in flight.
+A request's units are fixed by its plan (a range size from the planner's time
+estimate), and consecutive units carry the FP64 running sum in the
+accumulator, so every result is bit-identical to one whole contraction call
+and does not depend on what else is in flight.
 """
 from __future__ import annotations
 
@@ -75,11 +82,15 @@ class _Work:
     footprint: int = 0
     planned_at: float = 0.0
     started: float = 0.0
-    stream: object = None
+    stream: object = None     # stream index of the unit in flight (None: no unit in flight)
     event: object = None
     out: object = None
+    acc: object = None        # FP64 accumulator of the round's batches
     amps: object = None       # host copy of the requested batches' amplitudes
     cur_fixed: list = field(default_factory=list)  # batches of the round in flight
+    cursor: int = 0           # next slice group of the round
+    unit: int = 1             # slice groups per work unit
+    units_run: int = 0
     sub_done: int = 0         # sub-batches of 64 already sampled
     batches_done: int = 0     # batches contracted so far (all rounds)
     rounds: int = 0
@@ -91,7 +102,8 @@ class Server:
     """One GPU; `n_streams` concurrent requests; HBM admission budget in bytes."""
 
     def __init__(self, hbm_budget: int | None = None, n_streams: int = 4, plan_workers: int = 4,
-                 plan_flops_cap: float = 1e15, plan_opts: dict | None = None, device: int = 0):
+                 plan_flops_cap: float = 1e15, plan_opts: dict | None = None, device: int = 0,
+                 unit_seconds: float = 0.005):
         import torch
         from . import rqc
         self.rqc = rqc
@@ -131,16 +143,18 @@ class Server:
         self.plan_cache_cap = 256
         self.plan_cache_lock = threading.Lock()
         self.max_rounds = 16
+        # target device time of one work unit (the planner's estimate)
+        self.unit_seconds = unit_seconds
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self.free_streams = list(range(n_streams))
+        self.admitted: list = []
         self.planner = ThreadPoolExecutor(max_workers=plan_workers)
         self.ready: queue.Queue = queue.Queue()
         self.waiting: list = []
-        self.running: list = []
         self.lock = threading.Lock()
         self.stop = False
         self.stats = dict(submitted=0, completed=0, refused=0, errors=0, short=0, plan_cache_hits=0,
-                          extra_rounds=0)
+                          extra_rounds=0, units=0)
         self.loop = threading.Thread(target=self._run, daemon=True)
         self.loop.start()
 
@@ -203,7 +217,8 @@ class Server:
             w.plan = self._plan_for(w.req)
             w.info = rqc.plan_info(w.plan)
             o = len(w.req.open_qubits)
-            out_bytes = len(w.req.fixed_bits) * (8 << o) + 8 * w.req.n_samples
+            # outputs, the FP64 accumulator and the samples
+            out_bytes = len(w.req.fixed_bits) * (24 << o) + 8 * w.req.n_samples
             w.footprint = int(w.info["workspace_bytes"]) + out_bytes
             w.planned_at = time.perf_counter()
             flops = w.info["flops_per_batch"] * len(w.req.fixed_bits)
@@ -217,25 +232,44 @@ class Server:
         except Exception as e:  # planning failures are reported per request
             self._finish(w, "error", str(e))
 
-    def _launch(self, w: _Work, sid: int):
-        """Contract the round's batches (the request's own on the first round)."""
-        rqc, torch = self.rqc, self.torch
+    def _begin(self, w: _Work):
+        """Admission: the request's buffers, its unit size, its first round."""
+        torch = self.torch
         req = w.req
+        o = len(req.open_qubits)
+        n = len(req.fixed_bits)
+        w.started = time.perf_counter()
+        w.cur_fixed = list(req.fixed_bits)
+        w.out = torch.empty((n, 1 << o, 2), dtype=torch.float32, device="cuda")
+        w.acc = torch.empty((n, 1 << o, 2), dtype=torch.float64, device="cuda")
+        groups = max(1, int(w.info["n_groups"]))
+        per_group = w.info["est_seconds"] * n / groups
+        w.unit = max(1, min(groups, int(self.unit_seconds / max(per_group, 1e-12))))
+        w.cursor = 0
+
+    def _launch_unit(self, w: _Work, sid: int):
+        """The request's next range of slice groups on stream sid; the round's
+        last unit also normalises into the output."""
+        rqc, torch = self.rqc, self.torch
         s = self.streams[sid]
         w.stream = sid
-        if w.rounds == 0:
-            w.started = time.perf_counter()
-            w.cur_fixed = list(req.fixed_bits)
-        o = len(req.open_qubits)
+        groups = int(w.info["n_groups"])
+        k = min(w.unit, groups - w.cursor)
+        nb = len(w.cur_fixed)
         with torch.cuda.stream(s):
-            if w.out is None:
-                w.out = torch.empty((len(req.fixed_bits), 1 << o, 2), dtype=torch.float32, device="cuda")
-            rqc.contract_amplitudes(w.plan, w.cur_fixed, w.out[:len(w.cur_fixed)], stream=s)
+            rqc.contract_groups(w.plan, w.cursor, k, w.cur_fixed, w.acc[:nb], stream=s)
+            w.cursor += k
+            if w.cursor >= groups:
+                rqc.finalize_amplitudes(w.plan, w.acc[:nb], nb, w.out[:nb], stream=s)
             w.event = torch.cuda.Event()
             w.event.record(s)
+        w.units_run += 1
+        with self.lock:
+            self.stats["units"] += 1
 
-    def _complete(self, w: _Work) -> bool:
-        """Sample the finished round; returns False when another round was launched."""
+    def _round_done(self, w: _Work) -> bool:
+        """After the round's last unit: copy out, sample.  Returns False when
+        another round (more batches for the samples) was started."""
         rqc, torch = self.rqc, self.torch
         req = w.req
         s = self.streams[w.stream]
@@ -259,14 +293,14 @@ class Server:
                 w.batches_done += len(w.cur_fixed)
                 if w.n_out < req.n_samples and req.more_fixed_bits is not None and w.rounds < self.max_rounds:
                     # expected yield about 1/alpha sample per sub-batch; at most
-                    # as many batches as the request's own buffer holds
+                    # as many batches as the request's own buffers hold
                     want = math.ceil(req.alpha * (req.n_samples - w.n_out) * 1.25 / (1 << (o - 6)))
                     k = max(1, min(len(req.fixed_bits), want))
                     w.cur_fixed = list(req.more_fixed_bits(w.batches_done, k))
+                    w.cursor = 0
                     w.rounds += 1
                     with self.lock:
                         self.stats["extra_rounds"] += 1
-                    self._launch(w, w.stream)
                     return False
             status = "ok" if w.n_out >= req.n_samples else "short"
             self._finish(w, status, amps=w.amps,
@@ -286,44 +320,59 @@ class Server:
             self.stats[key] += 1
         w.plan = None
         w.out = None
+        w.acc = None
         w.fut.set_result(r)
 
     def _run(self):
-        while not self.stop or self.waiting or self.running or not self.ready.empty():
+        while not self.stop or self.waiting or self.admitted or not self.ready.empty():
             progressed = False
             while True:
                 try:
                     self.waiting.append(self.ready.get_nowait())
                 except queue.Empty:
                     break
-            # admission in arrival order among planned requests
+            # admission in arrival order among planned requests, by HBM footprint
             self.waiting.sort(key=lambda x: x.req.arrival)
             still = []
             for w in self.waiting:
-                if self.free_streams and self.in_use + w.footprint <= self.budget:
-                    sid = self.free_streams.pop(0)
+                if self.in_use + w.footprint <= self.budget:
                     self.in_use += w.footprint
                     self.peak_in_use = max(self.peak_in_use, self.in_use)
                     try:
-                        self._launch(w, sid)
-                        self.running.append(w)
+                        self._begin(w)
+                        self.admitted.append(w)
                     except Exception as e:
                         self.in_use -= w.footprint
-                        self.free_streams.append(sid)
                         self._finish(w, "error", str(e))
                     progressed = True
                 else:
                     still.append(w)
             self.waiting = still
-            # completions
-            done = [w for w in self.running if w.event.query()]
-            for w in done:
+            # completed units
+            for w in [x for x in self.admitted if x.stream is not None and x.event.query()]:
                 progressed = True
-                if not self._complete(w):
-                    continue  # another round is in flight on the same stream
-                self.running.remove(w)
-                self.in_use -= w.footprint
-                self.free_streams.append(w.stream)
+                sid = w.stream
+                if w.cursor >= int(w.info["n_groups"]):
+                    if self._round_done(w):
+                        self.admitted.remove(w)
+                        self.in_use -= w.footprint
+                w.stream = None
+                self.free_streams.append(sid)
+            # each free stream takes the next unit of the earliest admitted
+            # request without a unit in flight
+            idle = sorted((x for x in self.admitted if x.stream is None), key=lambda x: x.req.arrival)
+            while self.free_streams and idle:
+                w = idle.pop(0)
+                sid = self.free_streams.pop(0)
+                try:
+                    self._launch_unit(w, sid)
+                except Exception as e:
+                    w.stream = None
+                    self.free_streams.append(sid)
+                    self.admitted.remove(w)
+                    self.in_use -= w.footprint
+                    self._finish(w, "error", str(e))
+                progressed = True
             if not progressed:
                 time.sleep(0.0002)
 

@@ -101,3 +101,18 @@ def test_gate_count_of_the_53_qubit_circuit():
     lines = [ln.split() for ln in text.splitlines()]
     want = sum(1 for w in lines if w and w[0] in ("sx", "sy", "sw", "fsim"))
     assert bench.gate_count(text) == want > 1000
+
+
+def test_serving_workload_text_follows_the_parameters():
+    """The serving line's workload string is built from the parameters the run
+    uses (shapes, cycles, amplitudes, samples, precision mix, cost cap)."""
+    kw = dict(bench.SERVE_KW)
+    text = bench.serve_workload_text(1000, kw, bench.SERVE_CAP)
+    qubits = sorted(r * c for r, c in kw["shapes"])
+    assert f"{qubits[0]}..{qubits[-1]} qubits" in text and "20..40 qubits" in text
+    assert f"{kw['cycles'][0]}..{kw['cycles'][1]} cycles" in text and "8..20 cycles" in text
+    assert f"2^{kw['log2_amps'][0]}..2^{kw['log2_amps'][1]} amplitudes" in text
+    assert f"{kw['samples'][0]}..{kw['samples'][1]} samples" in text
+    assert text.startswith("serving: 1000 seeded requests per load")
+    kw["cycles"] = (3, 5)
+    assert "3..5 cycles" in bench.serve_workload_text(10, kw, 1e9)

@@ -176,3 +176,44 @@ def test_user_path_and_legs_are_used(rqc):
     p = rqc.plan_create(c, [0, 1], dry_run=1, path=path, sliced_legs=[5])
     info = rqc.plan_info(p)
     assert info["n_steps"] == n_g - 1 and rqc.plan_sliced_legs(p) == [5]
+
+
+def test_annealing_refines_a_weak_search(rqc):
+    """Simulated annealing of tree and slicing (the optimiser Sec. I names for
+    T and I) from a 64-trial search of the 30-qubit circuit: the kept plan is
+    estimated faster, does fewer flops, keeps the 6 prescribed sliced legs and
+    round-trips through its path."""
+    cfg = synthetic.CONFIGS["mid"]
+    t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    c = rqc.load_circuit(t)
+    base = rqc.plan_create(c, cfg["open_qubits"], n_sliced_target=6, path_trials=64, path_seed=1, dry_run=1)
+    ann = rqc.plan_create(c, cfg["open_qubits"], n_sliced_target=6, path_trials=64, path_seed=1, dry_run=1,
+                          anneal_iters=200_000)
+    bi, ai = rqc.plan_info(base), rqc.plan_info(ann)
+    assert ai["n_sliced"] == 6
+    assert ai["est_seconds"] < 0.9 * bi["est_seconds"] and ai["flops_per_batch"] < bi["flops_per_batch"]
+    again = rqc.plan_create(c, cfg["open_qubits"], path=rqc.plan_path(ann), sliced_legs=rqc.plan_sliced_legs(ann),
+                            dry_run=1)
+    assert rqc.plan_info(again)["flops_per_batch"] == ai["flops_per_batch"]
+
+
+def test_plan_describe_lists_every_launch(rqc):
+    """rqc_plan_describe: one line per op of the launch program, with the
+    kernel each streaming step runs on and the GEMM shapes."""
+    cfg = synthetic.CONFIGS["mid"]
+    t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    p = rqc.plan_create(rqc.load_circuit(t), cfg["open_qubits"], n_sliced_target=6, path_seed=1, dry_run=1)
+    info = rqc.plan_info(p)
+    lines = rqc.plan_describe(p).splitlines()
+    ops = [ln.split() for ln in lines[1:]]
+    assert lines[0].startswith("#") and len(ops) == info["n_launches"] - 2  # + leaf select and accumulate
+    assert [int(o[0]) for o in ops] == list(range(len(ops)))
+    kinds = {o[1] for o in ops}
+    assert kinds <= {"small", "stream", "permute", "gemm"} and "gemm" in kinds and "stream" in kinds
+    streams = [o[2] for o in ops if o[1] == "stream"]
+    sk = info["stream_kernels"]
+    for k in ("mx2", "lk", "tile"):
+        assert streams.count(k) == sk[k]
+    assert streams.count("mx") + streams.count("mx-wide") == sk["mx"]
+    flops = sum(float(o[4]) for o in ops)
+    assert abs(flops * info["n_groups"] - info["flops_per_batch"]) <= 1e-6 * info["flops_per_batch"]

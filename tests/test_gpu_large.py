@@ -11,7 +11,9 @@ Pinned here:
   * slicing is a resolution of the identity (Sec. I): the FP64 sum over two
     batched groups of the share in one call equals the sum of two calls, and
     a group of slices equals, on the same tree, the sum over the same group
-    with one more leg sliced (a different slicing, different launch shapes).
+    with one more leg sliced (a different slicing, different launch shapes);
+  * the streaming steps on 2^30-element tensors (the matrix-core kernel's
+    64-bit addressed form) agree with the same slices on the vector kernels.
 The amplitudes themselves are otherwise unpinned at 53 qubits (no state vector
 of 53 qubits exists).
 """
@@ -23,6 +25,7 @@ import pytest
 
 import bench
 import synthetic
+from gpu_common import assert_close
 from oracle import circuit as oc
 from oracle import partial
 
@@ -39,7 +42,8 @@ def setup():
     text = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
     open_q = list(cfg["open_qubits"])
     c = rqc.load_circuit(text)
-    args = types.SimpleNamespace(path_trials=bench.LARGE_TRIALS, large_seeds=bench.LARGE_SEEDS)
+    args = types.SimpleNamespace(path_trials=bench.LARGE_TRIALS, large_seeds=bench.LARGE_SEEDS,
+                                 anneal_iters=bench.LARGE_ANNEAL)
     path, legs, _ = bench.plan_large(rqc, c, open_q, args)
     plan = rqc.plan_create(c, open_q, path=path, sliced_legs=legs, max_log2_tensor=30, max_log2_batched=30,
                            target_fidelity=bench.LARGE_F)
@@ -132,3 +136,47 @@ def test_another_slicing_of_the_same_tree_agrees(setup):
     scale = np.abs(a).max()
     assert scale > 0
     assert np.abs(a - b).max() <= 2e-5 * scale
+
+
+def test_matrix_core_and_vector_streams_agree_at_full_size(setup):
+    """Streaming steps on 2^30-element tensors in the 64-bit addressed
+    matrix-core form ("mx-wide"), on the searched 53-qubit plan before
+    annealing (which has such steps): the same tree and slices with every
+    streaming step on the vector kernels (checked against the oracle at small
+    sizes) agree to FP32 rounding."""
+    rqc, torch = setup.rqc, setup.torch
+    args = types.SimpleNamespace(path_trials=bench.LARGE_TRIALS, large_seeds=bench.LARGE_SEEDS, anneal_iters=0)
+    path, legs, _ = bench.plan_large(rqc, setup.c, setup.open_q, args)
+    plan = rqc.plan_create(setup.c, setup.open_q, path=path, sliced_legs=legs, max_log2_tensor=30,
+                           max_log2_batched=30, target_fidelity=bench.LARGE_F)
+    desc = rqc.plan_describe(plan)
+    assert " mx-wide " in desc, "the searched plan has no wide matrix-core streaming step"
+    plan_v = rqc.plan_create(setup.c, setup.open_q, path=path, sliced_legs=legs, max_log2_tensor=30,
+                             max_log2_batched=30, target_fidelity=bench.LARGE_F, no_matrix_core_streams=1)
+    assert " mx-wide " not in rqc.plan_describe(plan_v) and " mx " not in rqc.plan_describe(plan_v)
+    assert rqc.plan_info(plan_v)["fidelity"] == rqc.plan_info(plan)["fidelity"]
+    S, X, _ = rqc.plan_partial(plan)
+    info = rqc.plan_info(plan)
+    group = 1 << info["n_batched"]
+    batched = []
+    if info["n_batched"]:
+        full = rqc.plan_slices(plan, cap=group)
+        bits = 0
+        for sid in full:
+            bits |= sid ^ full[0]
+        batched = [v for t, v in enumerate(legs) if (bits >> t) & 1]
+    sel = bench.share_ids(legs, S, X[0], 2 * group, batched)
+    fb = [synthetic.fixed_bits(setup.n, setup.open_q, synthetic.FIXED_BITS_SEED + 2)]
+    shape = (1, 1 << len(setup.open_q), 2)
+    amps = torch.empty(shape, dtype=torch.float32, device="cuda")
+    a64 = torch.empty(shape, dtype=torch.float64, device="cuda")
+    v64 = torch.empty(shape, dtype=torch.float64, device="cuda")
+    rqc.contract_amplitudes(plan, fb, amps, a64, slice_ids=sel)
+    rqc.contract_amplitudes(plan_v, fb, amps, v64, slice_ids=sel)
+    torch.cuda.synchronize()
+    a = a64.cpu().numpy()[0]
+    v = v64.cpu().numpy()[0]
+    a = a[:, 0] + 1j * a[:, 1]
+    v = v[:, 0] + 1j * v[:, 1]
+    assert np.abs(a).max() > 0
+    assert_close(a, v, 1e-5, "matrix-core vs vector streams")

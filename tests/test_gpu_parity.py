@@ -96,6 +96,56 @@ def test_vector_streaming_kernels_match_oracle(rqc):
     assert seen["tile"] > 0 and seen["ky"] > 0 and seen["gen"] > 0, seen
 
 
+def test_annealed_plan_matches_oracle(rqc):
+    """A tree and slicing refined by simulated annealing (from a 16-trial
+    search) contract to the oracle's amplitudes."""
+    text = circuit(5, 5, 12, seed=8)
+    open_q = list(range(13, 25))
+    fixed = synthetic.fixed_bits_batch(25, open_q, 4100, 2)
+    ref = oracle_batches(text, fixed, open_q)
+    amps, _, info, p = run_amplitudes(rqc, text, open_q, fixed, n_sliced_target=3, path_trials=16, path_seed=2,
+                                      anneal_iters=100_000)
+    assert info["n_sliced"] == 3
+    for b in range(2):
+        assert_close(amps[b], ref[b], TOL, f"annealed plan batch {b}")
+
+
+@pytest.mark.parametrize("cache", [0, 1])
+def test_contract_in_group_units_is_bitwise_one_call(rqc, cache):
+    """rqc_contract_groups over consecutive ranges of the default slice groups,
+    then rqc_finalize_amplitudes, equals one rqc_contract_amplitudes call bit
+    for bit (the FP64 running sum is carried in the accumulator), with and
+    without the global cache; a range past the list is refused."""
+    import torch
+    text = circuit(4, 5, 12, seed=9)
+    open_q = list(range(10, 20))
+    fixed = synthetic.fixed_bits_batch(20, open_q, 4200, 3)
+    c = rqc.load_circuit(text)
+    p = rqc.plan_create(c, open_q, n_sliced_target=4, max_log2_batched=1, path_seed=4, global_cache=cache)
+    info = rqc.plan_info(p)
+    G = info["n_groups"]
+    assert G >= 4
+    shape = (3, 1 << len(open_q), 2)
+    one = torch.empty(shape, dtype=torch.float32, device="cuda")
+    one64 = torch.empty(shape, dtype=torch.float64, device="cuda")
+    rqc.contract_amplitudes(p, fixed, one, one64)
+    acc = torch.full(shape, float("nan"), dtype=torch.float64, device="cuda")  # overwritten by the first unit
+    cuts = [0, 1, G // 2, G - 1, G]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        rqc.contract_groups(p, a, b - a, fixed, acc)
+    units = torch.empty(shape, dtype=torch.float32, device="cuda")
+    units64 = torch.empty(shape, dtype=torch.float64, device="cuda")
+    rqc.finalize_amplitudes(p, acc, 3, units, units64)
+    torch.cuda.synchronize()
+    assert torch.equal(one, units) and torch.equal(one64, units64)
+    ref = oracle_batches(text, fixed, open_q)
+    a = units.cpu().numpy()
+    for b in range(3):
+        assert_close(a[b, :, 0] + 1j * a[b, :, 1], ref[b], TOL, f"group units batch {b}")
+    with pytest.raises(rqc.RqcError):
+        rqc.contract_groups(p, G - 1, 2, fixed, acc)
+
+
 def test_single_amplitude_and_scalar_outputs(rqc):
     """No open qubit: each batch is one amplitude."""
     text = circuit(3, 3, 5, seed=6)

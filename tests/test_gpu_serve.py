@@ -35,9 +35,15 @@ def mix(serve, n=10, seed=1):
 
 
 def test_mix_equals_alone_and_matches_oracle(serve):
+    """In the mix every request runs in work units of one slice group (a tiny
+    unit time), alone in its default units: bitwise the same either way."""
     reqs = mix(serve)
-    together, _ = run_all(serve, reqs, n_streams=4, plan_workers=4)
+    srv = serve.Server(n_streams=4, plan_workers=4, unit_seconds=1e-9)
+    together = [f.result(timeout=300) for f in [srv.submit(r) for r in reqs]]
+    units = srv.stats["units"]
+    srv.shutdown()
     assert all(r.status == "ok" for r in together), [r.message for r in together]
+    assert units > len(reqs)  # requests were split into several units
     for req, r in zip(reqs, together):
         alone, _ = run_all(serve, [req], n_streams=1, plan_workers=1)
         a = alone[0]
@@ -61,6 +67,7 @@ def test_admission_budget_and_refusals(serve):
     budget = fp[-1] + fp[-2]
     res, peak = run_all(serve, reqs, n_streams=4, hbm_budget=budget)
     assert all(r.status == "ok" for r in res)
+    assert all(r.n_samples == req.n_samples for r, req in zip(res, reqs))  # 'ok' means the full count
     assert peak <= budget
     # a request larger than the whole budget is refused
     res, _ = run_all(serve, reqs[:2], n_streams=2, hbm_budget=fp[0] // 2)
