@@ -192,15 +192,19 @@ class SamplerTimer:
                 "bytes": 0.0, "exec_flops": 0.0, "exec_kind": 0}
 
 
+# the sources that decide what a given tree executes: the kernels, the
+# lowering that picks their tiles and layouts, and the executor (the tree
+# search and the planner's estimates are covered by the tree digest instead)
+TRAFFIC_SOURCES = ("kernels.hip", "kernels.hpp", "lower.cpp", "runtime.hip")
+
+
 def source_sha256():
-    """One digest over the library sources (kernels and the lowering that
-    decides their tiles and layouts both change the traffic)."""
+    """One digest over the library sources that decide the traffic of a tree."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2112_15083_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".cpp", ".hpp")):
-            h.update(name.encode())
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()
 
 
@@ -502,6 +506,7 @@ def run_large(args, rqc, torch):
     flops_per_slice = info["flops_per_batch"] / info["n_slices"] if info["n_slices"] else 0.0
     step_s = elapsed / args.steps
     share_s = step_s * n_groups
+    split = large_split_precision(args, rqc, torch, circ, open_q, path, legs, plan, ids, G, n_groups, step_s, n, o)
     job_slices = info["n_slices"]
     n_shares = job_slices // LARGE_SHARE
     # fidelity estimate of the job (Sec. II.B-C): F from the norms; eps from the
@@ -534,6 +539,7 @@ def run_large(args, rqc, torch):
                             f"(accepted: {sum(r[0] for r in rec)} over {args.steps} steps)",
             "one_gpu_seconds_1e5_samples_extrapolated": share_s * n_shares * calls_1e5,
             "calls_for_1e5_samples": calls_1e5},
+        "split_precision": split,
         "config": {"workload": f"large: 6x9 grid minus (0,4), 53 qubits, 20 cycles, 2^{o} open batch, "
                                f"intermediates <= 2^30 elements; partial slicing at f = 2^-18: |I| = {len(legs)} "
                                f"sliced legs, k = {k} near-input partial legs, R on 2^{k} entries, "
@@ -559,6 +565,44 @@ def gate_count(text):
     vector code only takes circuits it can hold)."""
     from oracle import circuit as oc
     return len(oc.parse(text).gates)
+
+
+def large_split_precision(args, rqc, torch, circ, open_q, path, legs, plan, ids, G, n_groups, step_s, n, o,
+                          steps=3):
+    """The same share steps with the GEMMs in the split modes (fp16x3 with
+    power-of-two scaling, bf16x3), timed like the complex64 steps (profiled
+    plans), with each mode's FP64 result on one group of slices compared with
+    the complex64 plan's (no FP64 oracle exists at 53 qubits; at 30 qubits the
+    modes' errors against the oracle are in the tests)."""
+    out = {}
+    shape = (1, 1 << o, 2)
+    ref64 = torch.empty(shape, dtype=torch.float64, device="cuda")
+    amps = torch.empty(shape, dtype=torch.float32, device="cuda")
+    fb0 = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED)]
+    rqc.contract_amplitudes(plan, fb0, amps, ref64, slice_ids=ids[:G])
+    for name, prec in (("fp16x3", rqc.FP16X3), ("bf16x3", rqc.BF16X3)):
+        q = rqc.plan_create(circ, open_q, path=path, sliced_legs=legs, max_log2_tensor=30, max_log2_batched=30,
+                            target_fidelity=LARGE_F, precision=prec, profile=1)
+        m64 = torch.empty(shape, dtype=torch.float64, device="cuda")
+        rqc.contract_amplitudes(q, fb0, amps, m64, slice_ids=ids[:G])
+        torch.cuda.synchronize()
+        a = ref64.cpu().numpy()[0]
+        b = m64.cpu().numpy()[0]
+        rel = float(np.linalg.norm(b - a) / np.linalg.norm(a))
+        t0 = time.perf_counter()
+        for i in range(steps):
+            fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + 100 + i)]
+            g = (1 + i) % n_groups
+            rqc.contract_amplitudes(q, fb, amps, slice_ids=ids[g * G:(g + 1) * G])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        out[name] = {"ms_per_step": ms, "amplitudes_per_s": (1 << o) / (ms * 1e-3 * n_groups),
+                     "speedup_vs_complex64": 1e3 * step_s / ms, "rel_l2_vs_complex64_fp64_sum": rel,
+                     "steps": steps}
+        del q
+    out["note"] = ("contraction only (the complex64 step also samples); relative L2 difference of the FP64 slice "
+                   "sums of one group against the complex64 plan")
+    return out
 
 
 def cpu_baseline_large(text, o, gpu_note, budget_s=20.0):

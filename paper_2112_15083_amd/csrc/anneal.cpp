@@ -11,7 +11,10 @@
 //     or add one;
 //   * cost: log2 of the sum over steps of the time-like step cost (complex
 //     multiply-adds plus five per element moved, as the greedy search scores
-//     trees) with the sliced legs removed, plus |I| (the number of slices);
+//     trees, plus a fixed launch cost for every step too large for the fused
+//     small-subtree launch: without it the moves split the work into hundreds
+//     of tiny launches) with the sliced legs removed, plus |I| (the number of
+//     slices);
 //     every state keeps each tensor within the memory bound;
 //   * Metropolis acceptance at a temperature (in log2 units of the total) that
 //     falls geometrically from 0.01 to 1e-5 over the iterations: most moves
@@ -128,7 +131,7 @@ class Annealer {
     }
     double node_cost(int u) const {
         return step_time_cost(rank_of(L_(ca[u])), rank_of(L_(cb[u])), rank_union(L_(ca[u]), L_(cb[u])),
-                              rank_of(L_(u)));
+                              rank_of(L_(u)), true);
     }
     void recompute() {
         cost.assign(nt, 0.0);
@@ -158,8 +161,8 @@ class Annealer {
         }
         const int r_new = rank_of(nlg);
         if (M > 0 && r_new > M) return;
-        const double c_y = step_time_cost(rank_of(L_(x)), rank_of(L_(yj)), rank_union(L_(x), L_(yj)), r_new);
-        const double c_u = step_time_cost(rank_of(L_(yk)), r_new, rank_union(L_(yk), nlg), rank_of(L_(u)));
+        const double c_y = step_time_cost(rank_of(L_(x)), rank_of(L_(yj)), rank_union(L_(x), L_(yj)), r_new, true);
+        const double c_u = step_time_cost(rank_of(L_(yk)), r_new, rank_union(L_(yk), nlg), rank_of(L_(u)), true);
         const double nt_total = total - cost[y] - cost[u] + c_y + c_u;
         const double d = std::log2(std::max(nt_total, 1.0)) - std::log2(std::max(total, 1.0));
         if (d > 0 && std::uniform_real_distribution<double>(0.0, 1.0)(rng) >= std::exp2(-d / T)) return;
@@ -198,7 +201,7 @@ class Annealer {
             int ru = rank_union(L_(ca[u]), L_(cb[u]));
             if (remove >= 0 && (has(L_(ca[u]), remove) || has(L_(cb[u]), remove))) ru++;
             if (add >= 0 && (has(L_(ca[u]), add) || has(L_(cb[u]), add))) ru--;
-            t += step_time_cost(rk[ca[u]], rk[cb[u]], ru, rk[u]);
+            t += step_time_cost(rk[ca[u]], rk[cb[u]], ru, rk[u], true);
         }
         return {t, mx};
     }

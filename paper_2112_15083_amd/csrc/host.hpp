@@ -95,8 +95,9 @@ struct SearchResult {
     double log2cost = 0;
 };
 // Time-like cost of one pairwise step of ranks ra, rb (operands), runion
-// (their union) and rc (result): multiply-adds plus weighted elements moved.
-double step_time_cost(int ra, int rb, int runion, int rc);
+// (their union) and rc (result): multiply-adds plus weighted elements moved,
+// plus a fixed launch cost for unfused steps when `launches`.
+double step_time_cost(int ra, int rb, int runion, int rc, bool launches = false);
 // Simulated annealing of a tree and its sliced legs (anneal.cpp): `iters`
 // Metropolis moves from (t, sliced); slicing moves only if slice_moves (and
 // keeping |sliced| when n_target >= 0); every state within max_log2_tensor.

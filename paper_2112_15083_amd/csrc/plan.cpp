@@ -136,22 +136,24 @@ double estimate_seconds(const PlanCore &p) {
     double t = 20e-6;
     for (const Op &op : pg.ops) {
         double dt;
+        // fixed cost per launch: the smallest streaming launches measure ~10 us
+        // of kernel time on the 53-qubit plan, plus the gap to the next one
         if (op.kind == OP_GEMM) {
-            dt = std::max(op.flops / gemm_rate, op.bytes / 5.5e12) + 4e-6;
+            dt = std::max(op.flops / gemm_rate, op.bytes / 5.5e12) + 8e-6;
         } else if (op.kind == OP_SMALL) {
             dt = 70e-6;
         } else if (op.kind == OP_PERMUTE) {
-            dt = op.bytes / 5e12 + 4e-6;
+            dt = op.bytes / 5e12 + 8e-6;
         } else {
             // streaming kernels at their measured rates: matrix-core tiles
             // ~4.5 TB/s, long contractions ~2 TB/s plus their partial-sum pass,
             // the vector fallbacks under 1 TB/s
             const StreamOp &so = pg.streams[op.index];
             const double rate = so.mx || so.mx2 ? 4.5e12 : (so.lk ? 2e12 : 0.8e12);
-            dt = op.bytes / rate + 4e-6;
+            dt = op.bytes / rate + 10e-6;
             // a fused pair may be bound by its two matrix-core stages instead
-            if (so.mx2) dt = std::max(dt, op.flops / (0.5 * 157.3e12) + 4e-6);
-            if (so.lk && so.lk_split > 0) dt += 16.0 * std::exp2((double)(so.lk_split + so.nr + so.nf)) / 2e12 + 4e-6;
+            if (so.mx2) dt = std::max(dt, op.flops / (0.5 * 157.3e12) + 10e-6);
+            if (so.lk && so.lk_split > 0) dt += 16.0 * std::exp2((double)(so.lk_split + so.nr + so.nf)) / 2e12 + 8e-6;
         }
         t += (op.kind == OP_SMALL || op.dep) ? dt : w_indep * dt;
     }

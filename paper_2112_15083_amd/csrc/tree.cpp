@@ -100,10 +100,18 @@ double tree_log2_cost_sum(const Tree &t, const std::vector<Legs> &legs) {
 // (8 flops each at 157 TFLOP/s); a lower weight is used because small
 // operands are served from cache or LDS.
 static constexpr double kTraffic = 5.0;
+// With `launches`: a step with a tensor above 2^10 elements is a kernel
+// launch of its own (the smaller ones run fused in one launch of whole
+// subtrees), and a launch takes ~8 us however little it does, the time of
+// ~2^27 complex MACs on the matrix cores.  The greedy search scores without
+// it; the annealer, whose moves can split work into many small steps, with it.
+static constexpr double kLaunch = 134217728.0;
+static constexpr int kFusedMaxRank = 10;
 
-double step_time_cost(int ra, int rb, int runion, int rc) {
+double step_time_cost(int ra, int rb, int runion, int rc, bool launches) {
+    const double launch = launches && std::max(ra, std::max(rb, rc)) > kFusedMaxRank ? kLaunch : 0.0;
     return std::exp2((double)runion) +
-           kTraffic * (std::exp2((double)ra) + std::exp2((double)rb) + std::exp2((double)rc));
+           kTraffic * (std::exp2((double)ra) + std::exp2((double)rb) + std::exp2((double)rc)) + launch;
 }
 
 double tree_log2_time_cost(const Tree &t, const std::vector<Legs> &legs) {
