@@ -447,7 +447,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_wav
 // partial sums go to P[split][r][f] and k_stream_lk_sum adds the ranges in
 // order.
 template <int NC>
-__global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC >= 2 ? 3 : 4)))
+k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                    float2 *__restrict__ P, float2 *__restrict__ C,
                                                    const BitMap *__restrict__ maps, int nr, int kc, int nf, int ks) {
     constexpr int RS = 68, SB = NC == 1 ? 16 : 16 * NC + 16, NT = 16;
@@ -461,10 +462,15 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
     const int64_t n_items = (int64_t)1 << (nr - 6 + ks), G = gridDim.x;
     int64_t item = blockIdx.x;
     if (item >= n_items) return; // whole workgroup
+    // A chunk elements: when the tile's lowest bit is A's lowest (the maps are
+    // bit deposits, so then every element pair 2i, 2i + 1 is adjacent and 16-byte
+    // aligned), a thread loads four such pairs with 16-byte loads; otherwise
+    // eight single elements
+    const bool pairs = map_apply(maps[SM_EA], 1) == 1;
     int offA[8], sA[8], offB[4], sB[4];
 #pragma unroll
     for (int k = 0; k < 8; k++) {
-        const int e = tid + 256 * k;
+        const int e = pairs ? 2 * (tid + 256 * (k >> 1)) + (k & 1) : tid + 256 * k;
         offA[k] = (int)map_apply(maps[SM_EA], e);
         sA[k] = (int)map_apply(maps[SM_ER], e) * RS + 2 * (int)map_apply(maps[SM_EY], e);
     }
@@ -474,6 +480,18 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
         offB[k] = e < nBt ? (int)map_apply(maps[SM_EB], e) : 0;
         sB[k] = e < nBt ? 2 * (int)map_apply(maps[SM_BY], e) * SB + 2 * (int)map_apply(maps[SM_BF], e) : 0;
     }
+    // with one chunk range per row group: this thread's output elements of a
+    // work item (C offset from the item's base, LDS source), the same for every
+    // item, so the bit maps are evaluated once
+    const int nC = 64 << nf, FP = F + 2;
+    int offC[8], srcC[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int e = tid + 256 * k;
+        const bool on = ks == 0 && e < nC;
+        offC[k] = on ? (int)map_apply(maps[SM_EC], e) : 0;
+        srcC[k] = on ? (int)map_apply(maps[SM_ER2], e) * FP + (int)map_apply(maps[SM_EF], e) : 0;
+    }
     // B' columns 2f + d with f >= F (fewer than 8 new indices) stay zero: the
     // stagings only write the others
     for (int i = tid; i < 64 * SB; i += 256) TB[i] = 0.f;
@@ -481,8 +499,17 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
     auto load = [&](int64_t abase, int64_t bbase, int ch) {
         const int64_t ya = abase + map_apply(maps[SM_YA], (int64_t)ch << 5);
         const int64_t yb = bbase + map_apply(maps[SM_YB], (int64_t)ch << 5);
+        if (pairs) {
 #pragma unroll
-        for (int k = 0; k < 8; k++) pa[k] = A[ya + offA[k]];
+            for (int k = 0; k < 8; k += 2) {
+                const float4 v = *reinterpret_cast<const float4 *>(A + ya + offA[k]);
+                pa[k] = make_float2(v.x, v.y);
+                pa[k + 1] = make_float2(v.z, v.w);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; k++) pa[k] = A[ya + offA[k]];
+        }
 #pragma unroll
         for (int k = 0; k < 4; k++)
             if (tid + 256 * k < nBt) pb[k] = B[yb + offB[k]];
@@ -536,7 +563,6 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
         if (ks == 0) {
             // one chunk range: the 64 x F outputs go to C through LDS ([row][f],
             // row stride F+2, in TA's space), written in C's memory order
-            const int FP = F + 2;
 #pragma unroll
             for (int cb = 0; cb < NC; cb++) {
                 const int jp = col + 16 * cb, f = jp >> 1, d = jp & 1;
@@ -548,9 +574,9 @@ __global__ void __launch_bounds__(256) k_stream_lk(const float2 *__restrict__ A,
             __syncthreads();
             const float2 *TC = reinterpret_cast<const float2 *>(TA);
             float2 *cb = C + map_apply(maps[SM_RC], r0);
-            const int nC = 64 << nf;
-            for (int e = tid; e < nC; e += 256)
-                cb[map_apply(maps[SM_EC], e)] = TC[map_apply(maps[SM_ER2], e) * FP + map_apply(maps[SM_EF], e)];
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (tid + 256 * k < nC) cb[offC[k]] = TC[srcC[k]];
             __syncthreads(); // TA is staged again by the next work item
         } else {
             float *Pf = reinterpret_cast<float *>(P);
