@@ -225,6 +225,9 @@ struct GemmOp {     // C[b][m][n] = sum_k A[b][m][k] B[b][k][n] (complex)
     int64_t sa, sb, sc; // batch strides (elements)
     int ksplit = 1; // > 1: K in ksplit ranges, partial sums in w ([range][batch][m][n]), added in order
     Buf w;
+    // C's layout with the c_ins_bits low M bits placed between N bits
+    // c_ins_pos - 1 and c_ins_pos (0 bits: plain [m][n])
+    int c_ins_pos = 0, c_ins_bits = 0;
 };
 
 struct Op {

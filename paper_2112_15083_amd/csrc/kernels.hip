@@ -985,6 +985,15 @@ void launch_permute_value(const PermDesc &d, const float2 *src, float2 *dst, hip
 }
 
 // ------------------------------------------------------------------ complex GEMM, FP32 MFMA
+// Offset of C element (m, n) within one batch: [m][n], or with the t = ins_bits
+// low bits of m placed between bits s - 1 and s of n (s = ins_pos), for a
+// consumer whose tiles want those M legs among C's lowest positions.
+__device__ __forceinline__ int64_t gemm_c_off(int64_t m, int64_t n, int64_t N, int s, int t) {
+    if (t == 0) return m * N + n;
+    const int64_t lo_n = n & ((1LL << s) - 1), lo_m = m & ((1LL << t) - 1);
+    return lo_n | (lo_m << s) | ((n >> s) << (s + t)) | ((m >> t) * (N << t));
+}
+
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Block tile BM x BN complex outputs, BK complex k per stage, 4 waves in a
@@ -1029,6 +1038,8 @@ k_cgemm_f32(GemmArgs g) {
     const float2 *B = g.B + bz * g.sb;
     float2 *C = g.ksplit > 1 ? g.W + (krange * g.batch + bz) * g.M * g.N : g.C + bz * g.sc;
     const int64_t M = g.M, N = g.N, K = g.K;
+    // partial sums of a K range go to W as [m][n]; the final C takes C's layout
+    const int ins_pos = g.ksplit > 1 ? 0 : g.c_ins_pos, ins_bits = g.ksplit > 1 ? 0 : g.c_ins_bits;
 
     // per-thread global coordinates of its operand chunk
     int a_r, a_c, b_r, b_c; // A: (m or k row, offset), B likewise
@@ -1126,7 +1137,7 @@ k_cgemm_f32(GemmArgs g) {
                 const int64_t m = m0 + wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int64_t n = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
                 const float x1 = t1[i][j][v], x2 = t2[i][j][v];
-                C[m * N + n] = make_float2(x1 - x2, (t3[i][j][v] - x1) - x2);
+                C[gemm_c_off(m, n, N, ins_pos, ins_bits)] = make_float2(x1 - x2, (t3[i][j][v] - x1) - x2);
             }
 }
 
@@ -1207,6 +1218,8 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
     const float2 *B = g.B + bz * g.sb;
     float2 *C = g.ksplit > 1 ? g.W + (krange * g.batch + bz) * g.M * g.N : g.C + bz * g.sc;
     const int64_t M = g.M, N = g.N, K = g.K;
+    // partial sums of a K range go to W as [m][n]; the final C takes C's layout
+    const int ins_pos = g.ksplit > 1 ? 0 : g.c_ins_pos, ins_bits = g.ksplit > 1 ? 0 : g.c_ins_bits;
     int ea = 0, eb = 0;
     if (F16) {
         ea = split_exp(__uint_as_float(amax[0]));
@@ -1344,7 +1357,7 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
                     re = ldexpf(ldexpf(re, -ea), -eb);
                     im = ldexpf(ldexpf(im, -ea), -eb);
                 }
-                C[m * N + n] = make_float2(re, im);
+                C[gemm_c_off(m, n, N, ins_pos, ins_bits)] = make_float2(re, im);
             }
 }
 
@@ -1397,7 +1410,8 @@ void launch_gemm_tiles(const GemmArgs &g, int precision, unsigned *amax, hipStre
 
 // Split K: C = sum over ranges r (ascending) of W[r], one output per thread.
 __global__ void __launch_bounds__(256) k_gemm_ksum(const float2 *__restrict__ W, float2 *__restrict__ C,
-                                                   int64_t n, int64_t mn, int64_t sc, int ksplit) {
+                                                   int64_t n, int64_t mn, int64_t sc, int ksplit, int64_t N,
+                                                   int ins_pos, int ins_bits) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         float2 acc = W[i];
         for (int r = 1; r < ksplit; r++) {
@@ -1405,7 +1419,8 @@ __global__ void __launch_bounds__(256) k_gemm_ksum(const float2 *__restrict__ W,
             acc.x += x.x;
             acc.y += x.y;
         }
-        C[(i / mn) * sc + i % mn] = acc;
+        const int64_t e = i % mn;
+        C[(i / mn) * sc + gemm_c_off(e / N, e % N, N, ins_pos, ins_bits)] = acc;
     }
 }
 
@@ -1414,11 +1429,14 @@ void launch_gemm(const GemmArgs &g_in, int precision, unsigned *amax, hipStream_
     g.m_fast = g.N > g.M;
     if (g.ksplit < 1 || (g.ksplit > 1 && (!g.W || g.K % (8LL * g.ksplit) != 0)))
         fail(RQC_EPLAN, "GEMM K split does not fit its kernel");
+    if (g.c_ins_bits < 0 || g.c_ins_pos < 0 || (g.c_ins_bits > 0 && ((1LL << g.c_ins_pos) > g.N ||
+                                                                     (1LL << g.c_ins_bits) > g.M)))
+        fail(RQC_EPLAN, "GEMM output bit insertion does not fit its shape");
     launch_gemm_tiles(g, precision, amax, s);
     if (g.ksplit > 1) {
         const int64_t n = g.batch * g.M * g.N;
         hipLaunchKernelGGL(k_gemm_ksum, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 256 * 16)), dim3(256), 0, s,
-                           g.W, g.C, n, g.M * g.N, g.sc, g.ksplit);
+                           g.W, g.C, n, g.M * g.N, g.sc, g.ksplit, g.N, g.c_ins_pos, g.c_ins_bits);
     }
 }
 

@@ -35,6 +35,7 @@ struct GemmArgs {
     int m_fast = 0; // tile order: m fastest (set by the launcher)
     int ksplit = 1; // > 1: K in ksplit ranges, partial sums in W ([range][batch][m][n]), then added in order
     float2 *W = nullptr;
+    int c_ins_pos = 0, c_ins_bits = 0; // C layout: the low c_ins_bits M bits sit at N bit c_ins_pos
 };
 
 void launch_leaf_select(const float2 *full, float2 *leafbuf, const LeafSel *d_sel, int n_leaves,

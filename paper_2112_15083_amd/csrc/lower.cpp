@@ -480,6 +480,48 @@ struct Lowerer {
         return out;
     }
 
+    // Number of C's lowest positions (layout LC of tensor t) that the tile of
+    // a fused pair whose large operand is t would cover: the pair's contracted
+    // legs and, as in emit_fused, the two lowest rows that neither step
+    // batches over nor the second contracts.  0 when t is not such an operand.
+    int pair_tile_prefix(int t, const std::vector<int> &LC) {
+        const int p1 = parent[t];
+        if (p1 < 0 || in_small[p1] || gemm_worthy(p1) || !fusable(p1) || step_legs(p1).a != t) return 0;
+        const StepLegs u1 = step_legs(p1), u2 = step_legs(parent[p1]);
+        int n = 0, rows = 0;
+        for (int v : LC) {
+            if (contains(u1.k, v) || contains(u2.k, v)) n++;
+            else if (rows < 2 && contains(u1.rows, v) && !contains(u1.q, v) && !contains(u2.q, v)) n++, rows++;
+            else break;
+        }
+        return n;
+    }
+
+    // A GEMM whose result is a fused pair's large operand writes its output
+    // [M | N] with N lowest.  When N's lowest legs give the pair's tile fewer
+    // than four low bits (a 128-byte line), two tiles share every line and the
+    // operand is read twice.  If the first M legs are legs the pair contracts,
+    // putting them right after that N prefix lengthens the tile's run: returns
+    // how many M legs to insert (0: leave [M | N]).
+    int pair_tile_insert(int t, const std::vector<int> &fbord, const std::vector<int> &faord) {
+        std::vector<int> LC = fbord;
+        LC.insert(LC.end(), faord.begin(), faord.end());
+        const int s0 = pair_tile_prefix(t, LC);
+        if (s0 == 0 || s0 >= 4 || s0 >= (int)fbord.size()) return 0;
+        const int p1 = parent[t];
+        const StepLegs u1 = step_legs(p1), u2 = step_legs(parent[p1]);
+        for (int ins = 1; ins <= 3 && ins <= (int)faord.size(); ins++) {
+            const int v = faord[ins - 1];
+            if (!contains(u1.k, v) && !contains(u2.k, v)) return 0;
+            std::vector<int> W(fbord.begin(), fbord.begin() + s0);
+            W.insert(W.end(), faord.begin(), faord.begin() + ins);
+            W.insert(W.end(), fbord.begin() + s0, fbord.end());
+            W.insert(W.end(), faord.begin() + ins, faord.end());
+            if (pair_tile_prefix(t, W) >= 4) return ins;
+        }
+        return 0;
+    }
+
     // Emit the fused op for the pair (t1 -> t2); false if its tiles do not
     // allow the kernel's 16-byte accesses (then both steps run separately).
     bool emit_fused(int t1, int t2) {
@@ -969,6 +1011,19 @@ struct Lowerer {
         std::vector<int> LC = fbord;
         LC.insert(LC.end(), faord.begin(), faord.end());
         LC.insert(LC.end(), bord.begin(), bord.end());
+        if (const int ins = pair_tile_insert(t, fbord, faord); ins > 0) {
+            // the first `ins` M legs go between N legs so that a fused pair's
+            // tile covers C's lowest 16-byte-line bits (see pair_tile_insert)
+            const int s0 = pair_tile_prefix(t, LC);
+            std::vector<int> W(fbord.begin(), fbord.begin() + s0);
+            W.insert(W.end(), faord.begin(), faord.begin() + ins);
+            W.insert(W.end(), fbord.begin() + s0, fbord.end());
+            W.insert(W.end(), faord.begin() + ins, faord.end());
+            W.insert(W.end(), bord.begin(), bord.end());
+            LC = W;
+            g.c_ins_pos = s0;
+            g.c_ins_bits = ins;
+        }
         layout[t] = LC;
         g.c = materialise(t);
         if (a_tmp >= 0) touch(a_tmp);

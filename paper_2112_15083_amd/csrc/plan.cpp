@@ -590,6 +590,7 @@ std::string describe_program(const PlanCore &p) {
                           (long long)go.batch, (long long)go.M, (long long)go.N, (long long)go.K, go.a_kfast, go.b_nfast,
                           go.ksplit);
             shape = line;
+            if (go.c_ins_bits > 0) shape += " c_ins=" + std::to_string(go.c_ins_pos) + "/" + std::to_string(go.c_ins_bits);
             break;
         }
         }

@@ -399,6 +399,8 @@ float2 *run_group(rqc_plan *p, int phase, const ProjVals &vals, int64_t slot, hi
             ga.b_nfast = go.b_nfast;
             ga.ksplit = go.ksplit;
             ga.W = go.ksplit > 1 ? ptr(go.w) : nullptr;
+            ga.c_ins_pos = go.c_ins_pos;
+            ga.c_ins_bits = go.c_ins_bits;
             // executed: three FP32 real products per complex multiply-add, or
             // three bf16/fp16 products of the 2K-long real view per output part
             const bool split = p->opts.precision != RQC_C64 && go.K >= 16;
