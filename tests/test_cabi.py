@@ -224,3 +224,17 @@ def test_plan_describe_lists_every_launch(rqc):
     assert streams.count("mx") + streams.count("mx-wide") == sk["mx"]
     flops = sum(float(o[4]) for o in ops)
     assert abs(flops * info["n_groups"] - info["flops_per_batch"]) <= 1e-6 * info["flops_per_batch"]
+
+def test_gemm_feeding_a_fused_pair_inserts_its_leg(rqc):
+    """On the 30-qubit plan the GEMM whose result is the first fused pair's
+    large operand writes that result with one leg the pair contracts placed
+    at position 3 among its N legs (c_ins=3/1), so the pair's tile covers the
+    operand's four lowest bits (a whole 128-byte line); no other GEMM does."""
+    cfg = synthetic.CONFIGS["mid"]
+    t = synthetic.circuit_text(cfg["rows"], cfg["cols"], cfg["cycles"], cfg["seed"], cfg["removed"])
+    p = rqc.plan_create(rqc.load_circuit(t), cfg["open_qubits"], n_sliced_target=6, path_trials=65536, dry_run=1)
+    lines = rqc.plan_describe(p).splitlines()[1:]
+    ins = [ln.split() for ln in lines if "c_ins=" in ln]
+    assert len(ins) == 1 and ins[0][1] == "gemm" and ins[0][-1] == "c_ins=3/1"
+    nxt = [ln.split() for ln in lines if int(ln.split()[0]) == int(ins[0][0]) + 1]
+    assert nxt and nxt[0][2] == "mx2"

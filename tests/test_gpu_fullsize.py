@@ -5,7 +5,7 @@ written from the oracle's full state vector only).
 
 Bars (relative L2, and every entry within the element-wise bar of
 gpu_common.assert_close): complex64 1e-5, for the complex64 output and the
-FP64 copy of the same sum; on the 16-cycle workload also the split-precision
+FP64 copy of the same sum; on both workloads also the split-precision
 GEMMs on the same tree, bf16x3 2e-4 and fp16x3 1e-5 (derived from the 8- and
 11-bit significands of the split parts: x = hi + lo + d with |d| <= 2^-16 |x|
 for bf16 and 2^-22 |x| for fp16, accumulated over the plan's GEMM chain).
@@ -50,7 +50,8 @@ def _oracle_samples(a, fb, open_q, n, alpha, base, n_sub):
     return exp, idx, rst
 
 
-@pytest.mark.parametrize("name,modes", [("mid", ("C64",)), ("precision", ("C64", "BF16X3", "FP16X3"))])
+@pytest.mark.parametrize("name,modes", [("mid", ("C64", "BF16X3", "FP16X3")),
+                                        ("precision", ("C64", "BF16X3", "FP16X3"))])
 def test_full_size_batches_match_stored_oracle(name, modes):
     import torch
     if not torch.cuda.is_available():
