@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mx_wav
 // partial sums go to P[split][r][f] and k_stream_lk_sum adds the ranges in
 // order.
 template <int NC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC >= 2 ? 3 : 4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
                                                    float2 *__restrict__ P, float2 *__restrict__ C,
                                                    const BitMap *__restrict__ maps, int nr, int kc, int nf, int ks) {
@@ -551,12 +551,29 @@ k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
             // the next chunk, or the next work item's first chunk
             if (ch + 1 < c0 + nch) load(abase, bbase, ch + 1);
             else if (next < n_items) load(nabase, nbbase, nsp * nch);
+            // operands of SG s-steps at a time, the next SG read from LDS
+            // while these feed the matrix cores (two register slots)
+            constexpr int SG = NC >= 4 ? 2 : 4;
+            float av[2][SG], bv[2][SG][NC];
+            auto lds_ops = [&](int sl, int s0) {
 #pragma unroll
-            for (int s = 0; s < NT; s++) {
-                const float a = arow[4 * s];
+                for (int q = 0; q < SG; q++) {
+                    av[sl][q] = arow[4 * (s0 + q)];
 #pragma unroll
-                for (int cb = 0; cb < NC; cb++)
-                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bcol[4 * s * SB + 16 * cb], acc[cb], 0, 0, 0);
+                    for (int cb = 0; cb < NC; cb++) bv[sl][q][cb] = bcol[4 * (s0 + q) * SB + 16 * cb];
+                }
+            };
+            lds_ops(0, 0);
+#pragma unroll
+            for (int sg = 0; sg < NT / SG; sg++) {
+                const int sl = sg & 1;
+                if (sg + 1 < NT / SG) lds_ops(sl ^ 1, SG * (sg + 1));
+                __builtin_amdgcn_sched_barrier(0); // keep those reads ahead of these products
+#pragma unroll
+                for (int q = 0; q < SG; q++)
+#pragma unroll
+                    for (int cb = 0; cb < NC; cb++)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[sl][q], bv[sl][q][cb], acc[cb], 0, 0, 0);
             }
             __syncthreads();
         }
@@ -1127,7 +1144,22 @@ k_cgemm_f32(GemmArgs g) {
         __syncthreads();
     }
     // epilogue: 32x32 accumulator, lane holds column lane%32 and rows
-    // 8*(v/4) + 4*(lane/32) + v%4
+    // 8*(v/4) + 4*(lane/32) + v%4.  The plain [m][n] form is its own loop,
+    // so that its addresses stay incremental.
+    if (ins_bits) {
+#pragma unroll
+        for (int i = 0; i < WM; i++)
+#pragma unroll
+            for (int j = 0; j < WN; j++)
+#pragma unroll
+                for (int v = 0; v < 16; v++) {
+                    const int64_t m = m0 + wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    const int64_t n = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
+                    const float x1 = t1[i][j][v], x2 = t2[i][j][v];
+                    C[gemm_c_off(m, n, N, ins_pos, ins_bits)] = make_float2(x1 - x2, (t3[i][j][v] - x1) - x2);
+                }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < WM; i++)
 #pragma unroll
@@ -1137,7 +1169,7 @@ k_cgemm_f32(GemmArgs g) {
                 const int64_t m = m0 + wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int64_t n = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
                 const float x1 = t1[i][j][v], x2 = t2[i][j][v];
-                C[gemm_c_off(m, n, N, ins_pos, ins_bits)] = make_float2(x1 - x2, (t3[i][j][v] - x1) - x2);
+                C[m * N + n] = make_float2(x1 - x2, (t3[i][j][v] - x1) - x2);
             }
 }
 
@@ -1344,6 +1376,25 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
         stage(std::integral_constant<int, 0>{}, kt);
         if (kt + 1 < nk) stage(std::integral_constant<int, 1>{}, kt + 1);
     }
+    // the plain [m][n] form is its own loop, so that its addresses stay incremental
+    if (ins_bits) {
+#pragma unroll
+        for (int i = 0; i < WM; i++)
+#pragma unroll
+            for (int j = 0; j < WN; j++)
+#pragma unroll
+                for (int v = 0; v < 16; v++) {
+                    const int64_t m = m0 + wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    const int64_t n = n0 + wn * (BN / 2) + j * 32 + (lane & 31);
+                    float re = cre[i][j][v], im = cim[i][j][v];
+                    if (F16) {
+                        re = ldexpf(ldexpf(re, -ea), -eb);
+                        im = ldexpf(ldexpf(im, -ea), -eb);
+                    }
+                    C[gemm_c_off(m, n, N, ins_pos, ins_bits)] = make_float2(re, im);
+                }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < WM; i++)
 #pragma unroll
@@ -1357,7 +1408,7 @@ __global__ void __launch_bounds__(256) k_cgemm_split(GemmArgs g, const unsigned 
                     re = ldexpf(ldexpf(re, -ea), -eb);
                     im = ldexpf(ldexpf(im, -ea), -eb);
                 }
-                C[gemm_c_off(m, n, N, ins_pos, ins_bits)] = make_float2(re, im);
+                C[m * N + n] = make_float2(re, im);
             }
 }
 
