@@ -474,11 +474,15 @@ k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
         offA[k] = (int)map_apply(maps[SM_EA], e);
         sA[k] = (int)map_apply(maps[SM_ER], e) * RS + 2 * (int)map_apply(maps[SM_EY], e);
     }
+    // B chunk elements with the new index f fastest across lanes: their two
+    // 8-byte LDS writes per element then fall in consecutive banks (with the
+    // chunk index y fastest, as in B's memory order, rows 2y SB apart hit two
+    // banks only); B is small and read from L2, so its gather costs little
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        const int e = tid + 256 * k;
-        offB[k] = e < nBt ? (int)map_apply(maps[SM_EB], e) : 0;
-        sB[k] = e < nBt ? 2 * (int)map_apply(maps[SM_BY], e) * SB + 2 * (int)map_apply(maps[SM_BF], e) : 0;
+        const int e = tid + 256 * k, f = e & (F - 1), yl = e >> nf;
+        offB[k] = e < nBt ? (int)(map_apply(maps[SM_YB], yl) + map_apply(maps[SM_FB], f)) : 0;
+        sB[k] = e < nBt ? 2 * yl * SB + 2 * f : 0;
     }
     // with one chunk range per row group: this thread's output elements of a
     // work item (C offset from the item's base, LDS source), the same for every
