@@ -385,31 +385,30 @@ LARGE_ANNEAL = 1_000_000 # annealing moves per refined tree, from the best seed
 def plan_large(rqc, circ, open_q, args):
     """Tree and sliced legs for the 53-qubit partial plan: a host-only search per
     seed; the plan with the smallest estimated total time of the whole job (all
-    2^|I| slices) wins.  Returns (path, legs, record)."""
-    best = None
-    tried = []
-
-    def consider(seed, anneal):
-        nonlocal best
+    2^|I| slices) wins.  Returns (path, legs, the records of every plan
+    considered)."""
+    def plan(seed, anneal):
         p = rqc.plan_create(circ, open_q, max_log2_tensor=30, n_sliced_target=-1, max_log2_batched=30,
                             path_trials=args.path_trials, path_seed=seed, target_fidelity=LARGE_F, dry_run=1,
                             anneal_iters=anneal)
         path, legs = rqc.plan_path(p), rqc.plan_sliced_legs(p)
-        # the same tree and legs with every leg summed: its estimate covers all slices
-        q = rqc.plan_create(circ, open_q, path=path, sliced_legs=legs, max_log2_batched=30, dry_run=1)
-        qi = rqc.plan_info(q)
-        tried.append({"seed": seed, "anneal_iters": anneal, "n_sliced": len(legs),
-                      "est_seconds_all_slices": qi["est_seconds"],
-                      "flops_per_slice": qi["flops_per_batch"] / qi["n_slices"]})
-        if best is None or qi["est_seconds"] < best[2]["est_seconds_all_slices"]:
-            best = (path, legs, tried[-1])
+        # a host-only partial plan covers every slice, its S legs looped
+        qi = rqc.plan_info(p)
+        return path, legs, {"seed": seed, "anneal_iters": anneal, "n_sliced": len(legs),
+                            "est_seconds_all_slices": qi["est_seconds"],
+                            "flops_per_slice": qi["flops_per_batch"] / qi["n_slices"]}
 
-    for seed in range(args.large_seeds):
-        consider(seed, 0)
-    # simulated annealing of tree and slicing from the best seed's search
+    results = [plan(seed, 0) for seed in range(args.large_seeds)]
+    # simulated annealing of tree and slicing from every seed's search (the
+    # best search result does not always anneal to the best plan), the seeds in
+    # parallel host threads (the library releases the interpreter while it plans)
     if getattr(args, "anneal_iters", 0) > 0:
-        consider(best[2]["seed"], args.anneal_iters)
-    return best[0], best[1], tried
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=args.large_seeds) as ex:
+            results += list(ex.map(lambda sd: plan(sd, args.anneal_iters), range(args.large_seeds)))
+    # the smallest estimate wins, the earlier entry on a tie
+    best = min(results, key=lambda r: r[2]["est_seconds_all_slices"])
+    return best[0], best[1], [r[2] for r in results]
 
 
 def share_ids(legs, S, x, count, batched):
@@ -549,7 +548,8 @@ def run_large(args, rqc, torch):
                    "flops_per_slice": flops_per_slice, "flops_per_share": flops_per_slice * LARGE_SHARE,
                    "gemm_flop_share": info["gemm_flop_share"], "max_log2_tensor": info["max_log2_tensor"],
                    "plan_seconds": {"tree_search": search_s, "plan_and_norms": norms_s},
-                   "search": tried, "launches_per_group": info["n_launches"],
+                   "search": tried, "search_chosen": min(tried, key=lambda r: r["est_seconds_all_slices"]),
+                   "launches_per_group": info["n_launches"],
                    "tree_sha256": tree_digest(rqc, plan), "kernel_seconds": class_seconds(op_recs),
                    "share_seconds_derived": share_s},
         "roofline": kernel_roofline(op_recs, None),

@@ -297,6 +297,9 @@ void plan_tree(PlanCore &p, const int32_t *path, int32_t n_path_pairs, const std
             q.tree = rs[i].tree;
             q.sliced = rs[i].sliced;
             q.user_legs = p.user_legs;
+            // a partial plan keeps its partially sliced legs looped: the
+            // estimate must not batch them
+            if (lc && !user_sliced) q.S = sliced_vertex_select(*lc, q.sliced, partial_k0(p.opts));
             try {
                 plan_finish(q);
                 p.candidates.push_back({rs[i].tree, rs[i].sliced, estimate_seconds(q)});
@@ -413,7 +416,8 @@ void plan_finish(PlanCore &p) {
     p.groups.clear();
     p.n_group_range = 0;
     const int nl = (int)p.looped.size();
-    if (p.S.empty()) {
+    if (p.S.empty() || p.X.empty()) {
+        // no partial selection yet (a host-only plan): every slice, S looped
         if (nl > 62) fail(RQC_EPLAN, "too many looped slice legs");
         p.n_group_range = (uint64_t)1 << nl; // groups 0 .. 2^nl - 1, not materialised
     } else {
