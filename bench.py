@@ -775,7 +775,8 @@ def run_verify(args, rqc, torch):
                             path_seed=args.path_seed)
     out = torch.empty((1, 1 << o, 2), dtype=torch.float32, device="cuda")
     samples = torch.zeros(1 << (o - 6), dtype=torch.int64, device="cuda")
-    need = VERIFY_BITS * (args.warmup + args.steps)
+    n_calls = max(1, args.warmup) + args.steps  # the first call fills the cache
+    need = VERIFY_BITS * n_calls
     drawn, seen, call = [], [], 0
     while len(drawn) < need:
         fb = [synthetic.fixed_bits(n, open_q, synthetic.FIXED_BITS_SEED + 500 + call)]
@@ -798,12 +799,15 @@ def run_verify(args, rqc, torch):
                            path_seed=args.path_seed, global_cache=1, profile=1)
     plan_s = time.perf_counter() - t0
     info = rqc.plan_info(plan)
-    vout = torch.empty((VERIFY_BITS, 1, 2), dtype=torch.float32, device="cuda")
-    ver = []
+    vall = torch.empty((n_calls * VERIFY_BITS, 1, 2), dtype=torch.float32, device="cuda")
+    part = torch.empty(n_calls, dtype=torch.float64, device="cuda")
 
     def step(i):
-        rqc.contract_amplitudes(plan, drawn[i * VERIFY_BITS:(i + 1) * VERIFY_BITS], vout, stream=stream)
-        ver.append(vout.cpu().numpy()[:, 0, :].copy())  # synchronises the stream
+        # exact amplitudes of the step's bitstrings, then their FP64 sum of Eq. (1)
+        v = vall[i * VERIFY_BITS:(i + 1) * VERIFY_BITS]
+        rqc.contract_amplitudes(plan, drawn[i * VERIFY_BITS:(i + 1) * VERIFY_BITS], v, stream=stream)
+        rqc.prob_sums(v, 1, VERIFY_BITS, n, part[i:i + 1], stream=stream)
+        stream.synchronize()
 
     t0 = time.perf_counter()
     step(0)  # fills the cache
@@ -820,12 +824,19 @@ def run_verify(args, rqc, torch):
     elapsed = time.perf_counter() - t_start
     op_recs = rqc.plan_profile_ops(plan)
     step_s = elapsed / args.steps
-    v = np.concatenate(ver)
+    # the samples' XEB (Eq. (1)) over every verified amplitude, on the GPU
+    k = n_calls * VERIFY_BITS
+    xeb_d = torch.empty(1, dtype=torch.float64, device="cuda")
+    sum_d = torch.empty(1, dtype=torch.float64, device="cuda")
+    rqc.prob_sums(vall, 1, k, n, sum_d, xeb_d, stream=stream)
+    stream.synchronize()
+    xeb = float(xeb_d.item())
+    v = vall.cpu().numpy()[:, 0, :]
     amps = v[:, 0].astype(np.float64) + 1j * v[:, 1]
-    ref = np.array(seen[:len(amps)])
+    ref = np.array(seen[:k])
     rel = float(np.linalg.norm(amps - ref) / np.linalg.norm(ref))
-    xeb = float((2.0 ** n) * np.mean(np.abs(amps) ** 2) - 1.0)
-    xeb_sigma = float(np.std((2.0 ** n) * np.abs(amps) ** 2) / np.sqrt(len(amps)))
+    xeb_sigma = float(np.std((2.0 ** n) * np.abs(amps) ** 2) / np.sqrt(k))
+    step_sums = part.cpu().numpy()
     per_bitstring = info["flops_per_batch"] - info["flops_cached"]
     line = {
         "metric": METRIC, "value": VERIFY_BITS / step_s, "unit": "amplitudes/s", "n_gpus": 1,
@@ -836,6 +847,7 @@ def run_verify(args, rqc, torch):
         "verify": {"bitstrings_verified": int(len(amps)), "samples_drawn": len(drawn),
                    "correlated_calls": call, "sampling_seconds": sample_s,
                    "xeb_of_samples": xeb, "xeb_sigma": xeb_sigma,
+                   "xeb_from_step_sums": float((2.0 ** n) * step_sums.sum() / k - 1.0),
                    "rel_l2_vs_sampled_batch_amplitudes": rel,
                    "cache_fill_and_first_step_ms": 1e3 * fill_s, "cache_gib": info["cache_bytes"] / 2 ** 30,
                    "flops_cached_share": info["flops_cached"] / info["flops_per_batch"],
@@ -844,7 +856,7 @@ def run_verify(args, rqc, torch):
         "config": {"workload": f"verify: the 30-qubit circuit (5x6 grid, {cfg['cycles']} cycles), samples drawn "
                                f"from correlated 2^{o} batches, exact amplitudes of {VERIFY_BITS} sampled "
                                f"bitstrings per step, one per batch with no open qubit, {info['n_slices']} slices, "
-                               f"global cache",
+                               f"global cache, then the step's FP64 sum of Eq. (1)",
                    "qubits": n, "flops_per_bitstring": per_bitstring, "n_slices": info["n_slices"],
                    "gemm_flop_share": info["gemm_flop_share"], "max_log2_tensor": info["max_log2_tensor"],
                    "plan_seconds": plan_s, "tree_sha256": tree_digest(rqc, plan),

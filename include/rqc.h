@@ -425,6 +425,26 @@ rqc_status rqc_select_top(const void *amps, uint64_t fixed_bits, const int32_t *
                           int32_t n_qubits, int64_t count, uint64_t *out_samples, void *hip_stream);
 
 /*
+ * FP64 probability sums (the reductions of Sec. II.A and Eq. (1)): for each
+ * of n_rows rows of row_len complex64 amplitudes,
+ *   sums[r] = sum_i p_ri with p_ri = (double)re^2 + (double)im^2,
+ * the squared norm of a batch, or, when the row holds the amplitudes of k =
+ * row_len sampled bitstrings of an n_qubits circuit, the sum in the linear
+ * cross-entropy benchmark of Eq. (1); then, if xeb is not NULL,
+ *   xeb[r] = 2^n_qubits * sums[r] / row_len - 1.
+ *   amps: device complex64 [n_rows][row_len] (interleaved re, im), contiguous.
+ *   sums, xeb: device double [n_rows]; xeb may be NULL.
+ * The order of the additions depends only on row_len (chunks of 8192 entries,
+ * fixed trees), so repeated calls give the same bits.  row_len = 0 gives sums
+ * of 0 (and RQC_EINVAL if xeb is asked); n_rows = 0 does nothing; n_rows *
+ * ceil(row_len / 8192) must stay below 2^31 (else RQC_EINVAL).  Asynchronous
+ * on hip_stream; uses the per-stream scratch block (8 bytes per 8192
+ * amplitudes).
+ */
+rqc_status rqc_prob_sums(const void *amps, int64_t n_rows, int64_t row_len, int32_t n_qubits, double *sums,
+                         double *xeb, void *hip_stream);
+
+/*
  * Kernel-level primitives (the contraction steps of Sec. I run on these; they
  * are exported for direct use and for testing each kernel variant).
  *

@@ -74,6 +74,13 @@ hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batc
 // Top-count selection (select.hip): `work` is device memory of at least
 // select_scratch_bytes(2^n_open) bytes; open_q is a host array.  Asynchronous.
 size_t select_scratch_bytes(int64_t n);
+// FP64 probability sums of n_rows rows of row_len amplitudes, and their XEB
+// (Eq. (1)) when xeb is not null; `work` is device memory of at least
+// prob_sums_scratch_bytes(n_rows, row_len) bytes.  n_rows * ceil(row_len /
+// 8192) < 2^31.  Asynchronous.
+size_t prob_sums_scratch_bytes(int64_t n_rows, int64_t row_len);
+void launch_prob_sums(const float2 *amps, int64_t n_rows, int64_t row_len, int n_qubits, double *sums, double *xeb,
+                      void *work, hipStream_t s);
 void launch_select_top(const float2 *amps, int n_open, const int32_t *open_q, uint64_t fixed, int64_t count,
                        uint64_t *out, void *work, hipStream_t s);
 

@@ -944,6 +944,27 @@ rqc_status rqc_select_top(const void *amps, uint64_t fixed_bits, const int32_t *
     });
 }
 
+rqc_status rqc_prob_sums(const void *amps, int64_t n_rows, int64_t row_len, int32_t n_qubits, double *sums,
+                         double *xeb, void *hip_stream) {
+    return guard([&] {
+        if (n_rows < 0 || row_len < 0) fail(RQC_EINVAL, "negative size");
+        if (n_rows == 0) return;
+        if (!sums || (row_len > 0 && !amps)) fail(RQC_EINVAL, "null argument");
+        if (xeb && (row_len == 0 || n_qubits < 1 || n_qubits > 64))
+            fail(RQC_EINVAL, "the XEB needs row_len >= 1 and n_qubits in 1..64");
+        const int64_t nchunk = (row_len + 8191) / 8192;
+        if (n_rows >= ((int64_t)1 << 31) || n_rows * nchunk >= ((int64_t)1 << 31))
+            fail(RQC_EINVAL, "too many rows or chunks for one launch");
+        check_device();
+        hipStream_t s = (hipStream_t)hip_stream;
+        StreamScratch &sc = stream_scratch(s);
+        std::lock_guard<std::mutex> lk(sc.mu);
+        void *w = scratch_reserve(sc, prob_sums_scratch_bytes(n_rows, row_len));
+        launch_prob_sums((const float2 *)amps, n_rows, row_len, n_qubits, sums, xeb, w, s);
+        HIP_OK(hipGetLastError());
+    });
+}
+
 rqc_status rqc_kernel_cgemm(const void *A, const void *B, void *C, int64_t batch, int64_t M, int64_t N, int64_t K,
                             int32_t a_kfast, int32_t b_nfast, int32_t precision, void *hip_stream) {
     return guard([&] {

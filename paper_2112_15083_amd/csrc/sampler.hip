@@ -233,6 +233,71 @@ hipError_t run_sampler(const float2 *amps, const uint64_t *fixed, int64_t n_batc
     return hipSuccess;
 }
 
+// FP64 probability sums over rows of amplitudes: the squared norm of a batch,
+// and the sum in the linear XEB of Eq. (1) when a row holds the amplitudes of
+// k sampled bitstrings (XEB = 2^n * sum / k - 1).  The order of the additions
+// depends only on row_len, so every run gives the same bits: a row splits into
+// chunks of kSumChunk entries; thread t of a chunk adds entries t, t + 256, ...
+// in turn, then the 256 thread sums are combined by a fixed halving tree; the
+// chunk sums of a row are combined the same way by one workgroup.
+constexpr int kSumThreads = 256;
+constexpr int64_t kSumChunk = 8192;
+
+__device__ __forceinline__ double block_tree_sum(double v, double *lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kSumThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] = lds[threadIdx.x] + lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    return lds[0];
+}
+
+// One workgroup per (row, chunk); block b = row * nchunk + chunk.
+__global__ void __launch_bounds__(kSumThreads) k_prob_chunks(const float2 *__restrict__ amps, int64_t row_len,
+                                                             int64_t nchunk, double *__restrict__ part) {
+    __shared__ double lds[kSumThreads];
+    const int64_t b = blockIdx.x;
+    const int64_t row = b / nchunk, c = b - row * nchunk;
+    const float2 *a = amps + row * row_len;
+    const int64_t lo = c * kSumChunk, hi = lo + kSumChunk < row_len ? lo + kSumChunk : row_len;
+    double s = 0.0;
+#pragma unroll 8
+    for (int64_t e = lo + threadIdx.x; e < hi; e += kSumThreads) s = s + prob(a[e]);
+    s = block_tree_sum(s, lds);
+    if (threadIdx.x == 0) part[b] = s;
+}
+
+// One workgroup per row: the row's chunk sums, then its XEB when asked.
+__global__ void __launch_bounds__(kSumThreads) k_prob_rows(const double *__restrict__ part, int64_t nchunk,
+                                                           int64_t row_len, int n_qubits, double *__restrict__ sums,
+                                                           double *__restrict__ xeb) {
+    __shared__ double lds[kSumThreads];
+    const int64_t row = blockIdx.x;
+    double s = 0.0;
+    for (int64_t c = threadIdx.x; c < nchunk; c += kSumThreads) s = s + part[row * nchunk + c];
+    s = block_tree_sum(s, lds);
+    if (threadIdx.x == 0) {
+        sums[row] = s;
+        if (xeb) xeb[row] = ldexp(s / (double)row_len, n_qubits) - 1.0;
+    }
+}
+
+size_t prob_sums_scratch_bytes(int64_t n_rows, int64_t row_len) {
+    const int64_t nchunk = (row_len + kSumChunk - 1) / kSumChunk;
+    return align256((size_t)(n_rows * nchunk) * sizeof(double));
+}
+
+void launch_prob_sums(const float2 *amps, int64_t n_rows, int64_t row_len, int n_qubits, double *sums, double *xeb,
+                      void *work, hipStream_t s) {
+    const int64_t nchunk = (row_len + kSumChunk - 1) / kSumChunk;
+    double *part = (double *)work;
+    if (nchunk > 0) hipLaunchKernelGGL(k_prob_chunks, dim3((unsigned)(n_rows * nchunk)), dim3(kSumThreads), 0, s,
+                                       amps, row_len, nchunk, part);
+    hipLaunchKernelGGL(k_prob_rows, dim3((unsigned)n_rows), dim3(kSumThreads), 0, s, (const double *)part, nchunk,
+                       row_len, n_qubits, sums, xeb);
+}
+
 // ------------------------------------------------------------ fixed scratch
 // The scratch of rqc_rejection_sample_static: one array per device, held until
 // the process ends.  On the host its name is a stand-in, not a device address,

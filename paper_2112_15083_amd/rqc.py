@@ -129,6 +129,7 @@ _sig = {
                              ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
                              ctypes.POINTER(SampleStats), _P],
     "rqc_select_top": [_P, ctypes.c_uint64, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P],
+    "rqc_prob_sums": [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P, _P],
     "rqc_rejection_sample_static": [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                     ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64),
@@ -384,6 +385,13 @@ def select_top(amps, fixed_bits, open_qubits, n_qubits, count, out_samples, stre
     ascending batch index (asynchronous)."""
     _check(_lib.rqc_select_top(_ptr(amps), int(fixed_bits) & (2 ** 64 - 1), _i32(list(open_qubits)),
                                len(open_qubits), n_qubits, count, _ptr(out_samples), _stream(stream)))
+
+
+def prob_sums(amps, n_rows, row_len, n_qubits, sums, xeb=None, stream=None):
+    """FP64 sums of |a|^2 over each of n_rows rows of row_len amplitudes, and
+    the linear XEB 2^n * sum / row_len - 1 of each row into `xeb` when given
+    (asynchronous)."""
+    _check(_lib.rqc_prob_sums(_ptr(amps), n_rows, row_len, n_qubits, _ptr(sums), _ptr(xeb), _stream(stream)))
 
 
 def kernel_cgemm(A, B, C, batch, M, N, K, a_kfast=1, b_nfast=1, precision=C64, stream=None):

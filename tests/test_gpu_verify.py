@@ -11,8 +11,8 @@ the plan may keep its bitstring-independent subtrees in the global cache.
   * Samples drawn by the library's sampler from correlated 2^12 batches of the
     same circuit, verified on the no-open-qubit plan: each verified amplitude
     agrees with the one the sampler saw (another contraction tree), and the
-    samples' XEB from the verified probabilities equals the oracle's XEB of
-    the same bitstrings and lies within 5 sigma of its expectation
+    samples' XEB from the verified probabilities (summed in FP64 on the GPU)
+    equals the oracle's XEB of the same bitstrings and lies within 5 sigma of its expectation
     2^n sum p^2 - 1 (from the oracle's full vector).
 """
 import math
@@ -22,6 +22,7 @@ import pytest
 
 import synthetic
 from gpu_common import assert_close
+from oracle import stats as ostats
 from oracle import sv as osv
 
 pytestmark = pytest.mark.gpu
@@ -104,10 +105,17 @@ def test_sample_xeb_from_verified_amplitudes(lib, circuit20):
     v = _verify(rqc, torch, vplan, drawn).cpu().numpy()[:, 0, :]
     amps = v[:, 0].astype(np.float64) + 1j * v[:, 1]
     assert_close(amps, np.array(seen), TOL, "verified vs sampled batch amplitudes")
-    p_ver = np.abs(amps) ** 2
+    # the samples' XEB of Eq. (1) from the verified amplitudes, reduced on the GPU
+    vd = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    sum_d = torch.empty(1, dtype=torch.float64, device="cuda")
+    xeb_d = torch.empty(1, dtype=torch.float64, device="cuda")
+    rqc.prob_sums(vd, 1, len(drawn), n, sum_d, xeb_d)
+    torch.cuda.synchronize()
+    xeb_ver = float(xeb_d.item())
+    p_ver = v[:, 0].astype(np.float64) ** 2 + v[:, 1].astype(np.float64) ** 2
+    assert abs(xeb_ver - ostats.xeb(n, p_ver)) <= 1e-12 * (abs(xeb_ver) + 1.0)
     p_ora = np.array([abs(osv.batch_amplitudes(sv, b, [])[0]) ** 2 for b in drawn])
-    xeb_ver = (2.0 ** n) * p_ver.mean() - 1.0
-    xeb_ora = (2.0 ** n) * p_ora.mean() - 1.0
+    xeb_ora = ostats.xeb(n, p_ora)
     assert abs(xeb_ver - xeb_ora) <= 1e-4 * max(1.0, abs(xeb_ora))
     p_all = np.abs(sv) ** 2
     expect = (2.0 ** n) * float((p_all ** 2).sum()) - 1.0
