@@ -295,6 +295,13 @@ rqc_status rqc_plan_partial(const rqc_plan *p, int32_t *S, int32_t capS, uint64_
 rqc_status rqc_plan_slices(const rqc_plan *p, uint64_t *ids, int64_t cap, int64_t *count);
 rqc_status rqc_plan_profile(const rqc_plan *p, rqc_profile_t *out);
 rqc_status rqc_plan_profile_reset(rqc_plan *p);
+/* With profile = 1: time only the launches of the classes whose bit
+   (1 << RQC_K_*) is set in mask (every class until this is called).  Each
+   timed launch records two HIP events on its stream, which costs a few
+   microseconds per launch; timing one class leaves the others' launches
+   back to back.  Applies to later calls; bits at RQC_K_CLASSES or above give
+   RQC_EINVAL. */
+rqc_status rqc_plan_profile_classes(rqc_plan *p, uint32_t mask);
 /* The same profile split by op of the launch program (host array of cap
    records; *count receives the number of records).  Synchronises on the
    profiled work. */

@@ -111,7 +111,8 @@ struct rqc_plan : PlanCore {
     // global cache) and records its own end
     hipEvent_t done = nullptr;
     bool done_recorded = false;
-    // profiling
+    // profiling: with opts.profile, the classes whose bit is set get events
+    uint32_t prof_mask = 0xFFFFFFFFu;
     rqc_profile_t prof{};
     std::map<std::pair<int, int>, rqc_op_profile_t> op_prof; // (class, program op) -> totals
     std::vector<PendingEvent> pending;
@@ -237,16 +238,18 @@ struct Timer {
     int cls, op;
     double f, b, xf;
     int xk;
+    bool on;
     hipEvent_t a{};
     Timer(rqc_plan *p_, hipStream_t s_, int c, double f_, double b_, int op_ = -1, double xf_ = 0, int xk_ = 0)
         : p(p_), s(s_), cls(c), op(op_), f(f_), b(b_), xf(xf_), xk(xk_) {
-        if (p->opts.profile) {
+        on = p->opts.profile && ((p->prof_mask >> c) & 1u);
+        if (on) {
             a = p->ev();
             HIP_OK(hipEventRecord(a, s));
         }
     }
     ~Timer() noexcept(false) {
-        if (p->opts.profile) {
+        if (on) {
             hipEvent_t e = p->ev();
             HIP_OK(hipEventRecord(e, s));
             p->pending.push_back({cls, op, a, e, f, b, xf, xk});
@@ -722,6 +725,14 @@ rqc_status rqc_plan_profile_reset(rqc_plan *p) {
         p->flush_profile();
         p->prof = rqc_profile_t{};
         p->op_prof.clear();
+    });
+}
+
+rqc_status rqc_plan_profile_classes(rqc_plan *p, uint32_t mask) {
+    return guard([&] {
+        if (!p) fail(RQC_EINVAL, "null plan");
+        if (mask >> RQC_K_CLASSES) fail(RQC_EINVAL, "unknown kernel class in the mask");
+        p->prof_mask = mask;
     });
 }
 

@@ -117,6 +117,7 @@ _sig = {
     "rqc_plan_slices": [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
     "rqc_plan_profile": [_P, ctypes.POINTER(Profile)],
     "rqc_plan_profile_reset": [_P],
+    "rqc_plan_profile_classes": [_P, ctypes.c_uint32],
     "rqc_plan_profile_ops": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "rqc_contract_amplitudes": [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P],
     "rqc_contract_groups": [_P, ctypes.c_int64, ctypes.c_int64, _P, ctypes.c_int64, _P, _P],
@@ -326,6 +327,14 @@ def plan_profile_ops(p: Plan) -> list:
 
 def plan_profile_reset(p: Plan):
     _check(_lib.rqc_plan_profile_reset(p.handle))
+
+
+def plan_profile_classes(p: Plan, classes):
+    """Time only the launches of these classes (names as in K_NAMES)."""
+    mask = 0
+    for c in classes:
+        mask |= 1 << K_NAMES.index(c)
+    _check(_lib.rqc_plan_profile_classes(p.handle, mask))
 
 
 def contract_amplitudes(p: Plan, fixed_bits, out_amps, out_f64=None, slice_ids=None, stream=None):

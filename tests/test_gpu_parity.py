@@ -167,6 +167,42 @@ def test_gemm_steps_are_exercised(rqc):
     assert info["gemm_flop_share"] > 0
 
 
+def test_profiling_one_class_leaves_results_unchanged(rqc):
+    """Timing only some kernel classes (rqc_plan_profile_classes): only their
+    launches are recorded, with the same counts as when every class is timed,
+    and the amplitudes are bitwise those of the unprofiled plan."""
+    import torch
+    text = circuit(4, 5, 14, seed=7)
+    open_q = list(range(8, 20))
+    fixed = synthetic.fixed_bits_batch(20, open_q, 2000, 2)
+    c = rqc.load_circuit(text)
+    base = rqc.plan_create(c, open_q, n_sliced_target=2, path_seed=3)
+    opts = dict(path=rqc.plan_path(base), sliced_legs=rqc.plan_sliced_legs(base))
+    outs, recs = [], []
+    for prof, classes in ((0, None), (1, None), (1, ["gemm"]), (1, ["stream", "permute"])):
+        p = rqc.plan_create(c, open_q, profile=prof, **opts)
+        if classes:
+            rqc.plan_profile_classes(p, classes)
+        out = torch.empty((2, 1 << len(open_q), 2), dtype=torch.float32, device="cuda")
+        rqc.contract_amplitudes(p, fixed, out)
+        torch.cuda.synchronize()
+        outs.append(out.cpu())
+        recs.append(rqc.plan_profile_ops(p) if prof else [])
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    every = {}
+    for r in recs[1]:
+        every[r["cls"]] = every.get(r["cls"], 0) + r["launches"]
+    assert every.get("gemm", 0) > 0 and len(every) > 2
+    for got, classes in ((recs[2], {"gemm"}), (recs[3], {"stream", "permute"})):
+        counts = {}
+        for r in got:
+            counts[r["cls"]] = counts.get(r["cls"], 0) + r["launches"]
+        assert set(counts) <= classes and counts == {k: v for k, v in every.items() if k in classes}
+    with pytest.raises(rqc.RqcError):
+        rqc._check(rqc._lib.rqc_plan_profile_classes(base.handle, 1 << 8))  # no such class
+
+
 def test_custom_slice_lists_sum_to_full(rqc):
     """Sum over any split of the slice list equals the full result (slices are a
     resolution of the identity, Sec. I)."""
