@@ -499,10 +499,22 @@ k_stream_lk(const float2 *__restrict__ A, const float2 *__restrict__ B,
     // B' columns 2f + d with f >= F (fewer than 8 new indices) stay zero: the
     // stagings only write the others
     for (int i = tid; i < 64 * SB; i += 256) TB[i] = 0.f;
+    // A and B offsets of each chunk's first contracted element, evaluated once
+    // per workgroup (up to 64 chunks): a bit map costs a chain of dependent
+    // scalar loads, which would otherwise sit before every chunk's loads
+    __shared__ int64_t YT[2][64];
+    const int n_ch = 1 << (kc - 5);
+    const bool ytab = n_ch <= 64;
+    if (ytab)
+        for (int c = tid; c < n_ch; c += 256) {
+            YT[0][c] = map_apply(maps[SM_YA], (int64_t)c << 5);
+            YT[1][c] = map_apply(maps[SM_YB], (int64_t)c << 5);
+        }
+    __syncthreads();
     float2 pa[8], pb[4];
     auto load = [&](int64_t abase, int64_t bbase, int ch) {
-        const int64_t ya = abase + map_apply(maps[SM_YA], (int64_t)ch << 5);
-        const int64_t yb = bbase + map_apply(maps[SM_YB], (int64_t)ch << 5);
+        const int64_t ya = abase + (ytab ? YT[0][ch] : map_apply(maps[SM_YA], (int64_t)ch << 5));
+        const int64_t yb = bbase + (ytab ? YT[1][ch] : map_apply(maps[SM_YB], (int64_t)ch << 5));
         if (pairs) {
 #pragma unroll
             for (int k = 0; k < 8; k += 2) {
