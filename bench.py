@@ -379,7 +379,7 @@ LARGE_F = 2.0 ** -18     # target fidelity: the kept fraction 2^10 / 2^28
 LARGE_SHARE = 1 << 10    # slices in one GPU's share
 LARGE_TRIALS = 4096      # tree-search trials per seed
 LARGE_SEEDS = 4          # seeds searched; the best estimated job time is kept
-LARGE_ANNEAL = 1_000_000 # annealing moves per refined tree, from the best seed
+LARGE_ANNEAL = 3_000_000 # annealing moves per refined tree, for every seed
 
 
 def plan_large(rqc, circ, open_q, args):
