@@ -19,8 +19,14 @@ Other workloads (--config):
   precision  5x6 grid, 16 cycles, 10 sliced legs (1024 slices), 2^14 batch,
              in complex64 / bf16x3 / fp16x3 (--precision)
   tiny       3x4 grid, 8 cycles, all 12 qubits open
+  spoof      53 qubits, 12 cycles, one 2^25-amplitude batch at fidelity f
+             through partial slicing, then the top r of it selected on the GPU
+             (linear-XEB spoofing, Sec. III.B)
+  verify     the mid circuit: exact amplitudes of sampled bitstrings, 64 per
+             step, one batch each with no open qubit, and their FP64 XEB sum
   --serve    the serving loop on a Poisson stream of synthetic requests
-  --copy-calibration  a plain 1 GiB device copy, for scaling HBM counters
+  --copy-calibration  a plain 1 GiB device copy, the check of the HBM request
+             counters (they read 1 GiB each way for it)
 
 Planning is reported separately (plan_seconds) and is not part of a step.
 """
