@@ -44,7 +44,9 @@ def setup():
     c = rqc.load_circuit(text)
     args = types.SimpleNamespace(path_trials=bench.LARGE_TRIALS, large_seeds=bench.LARGE_SEEDS,
                                  anneal_iters=bench.LARGE_ANNEAL)
-    path, legs, _ = bench.plan_large(rqc, c, open_q, args)
+    # the benchmark's plan: the stored result of its search when it matches
+    stored = bench.stored_large_plan(text, args)
+    path, legs, _ = stored if stored is not None else bench.plan_large(rqc, c, open_q, args)
     plan = rqc.plan_create(c, open_q, path=path, sliced_legs=legs, max_log2_tensor=30, max_log2_batched=30,
                            target_fidelity=bench.LARGE_F)
     return types.SimpleNamespace(rqc=rqc, torch=torch, text=text, open_q=open_q, c=c, path=path, legs=legs,
