@@ -1041,7 +1041,10 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // 3 * 16 * (BM / 64) * (BN / 64) registers per lane
 constexpr int gemm_waves(int BM, int BN) { return BM * BN > 8192 ? 2 : BM * BN > 4096 ? 3 : 4; }
 
-template <int BM, int BN, int A_KFAST, int B_NFAST>
+// INS: C takes the bit-inserted layout (gemm_c_off); a separate instance, so
+// that the plain [m][n] epilogue keeps its registers (the inserted form's
+// addresses made the 128 x 128 instance spill, about 10 % of a K = 64 GEMM)
+template <int BM, int BN, int A_KFAST, int B_NFAST, bool INS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves(BM, BN))))
 k_cgemm_f32(GemmArgs g) {
     constexpr int BK = 8;
@@ -1072,7 +1075,8 @@ k_cgemm_f32(GemmArgs g) {
     float2 *C = g.ksplit > 1 ? g.W + (krange * g.batch + bz) * g.M * g.N : g.C + bz * g.sc;
     const int64_t M = g.M, N = g.N, K = g.K;
     // partial sums of a K range go to W as [m][n]; the final C takes C's layout
-    const int ins_pos = g.ksplit > 1 ? 0 : g.c_ins_pos, ins_bits = g.ksplit > 1 ? 0 : g.c_ins_bits;
+    // (the launcher picks INS only when the GEMM writes C itself with inserted bits)
+    const int ins_pos = INS ? g.c_ins_pos : 0, ins_bits = INS ? g.c_ins_bits : 0;
 
     // per-thread global coordinates of its operand chunk
     int a_r, a_c, b_r, b_c; // A: (m or k row, offset), B likewise
@@ -1162,7 +1166,7 @@ k_cgemm_f32(GemmArgs g) {
     // epilogue: 32x32 accumulator, lane holds column lane%32 and rows
     // 8*(v/4) + 4*(lane/32) + v%4.  The plain [m][n] form is its own loop,
     // so that its addresses stay incremental.
-    if (ins_bits) {
+    if constexpr (INS) {
 #pragma unroll
         for (int i = 0; i < WM; i++)
 #pragma unroll
@@ -1464,13 +1468,20 @@ static void split_gemm(const GemmArgs &g, unsigned *amax, hipStream_t s) {
     else split_dispatch<64, 64, F16>(g, amax, s);
 }
 
+template <int BM, int BN, bool INS>
+static void gemm_dispatch_ins(const GemmArgs &g, hipStream_t s) {
+    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch * g.ksplit));
+    if (g.a_kfast && g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 1, INS>), grid, dim3(256), 0, s, g);
+    else if (g.a_kfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 0, INS>), grid, dim3(256), 0, s, g);
+    else if (g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 1, INS>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 0, INS>), grid, dim3(256), 0, s, g);
+}
+
 template <int BM, int BN>
 static void gemm_dispatch(const GemmArgs &g, hipStream_t s) {
-    dim3 grid((unsigned)((g.N / BN) * (g.M / BM) * g.batch * g.ksplit));
-    if (g.a_kfast && g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 1>), grid, dim3(256), 0, s, g);
-    else if (g.a_kfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 1, 0>), grid, dim3(256), 0, s, g);
-    else if (g.b_nfast) hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 1>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_cgemm_f32<BM, BN, 0, 0>), grid, dim3(256), 0, s, g);
+    // with split K the tiles write partial sums as [m][n]; k_gemm_ksum inserts
+    if (g.c_ins_bits > 0 && g.ksplit == 1) gemm_dispatch_ins<BM, BN, true>(g, s);
+    else gemm_dispatch_ins<BM, BN, false>(g, s);
 }
 
 void launch_gemm_tiles(const GemmArgs &g, int precision, unsigned *amax, hipStream_t s);
